@@ -1,0 +1,248 @@
+"""Seeded synthetic inputs shaped like the paper's image stacks.
+
+This module draws inputs only: science images, variance planes, masks,
+observation times, a PSF kernel and a velocity grid.  It holds none of the
+search's arithmetic (no likelihood planes, no displacements, no sums, no
+scores), so both the oracle-based tests and the HIP path can consume the same
+bytes.
+
+Stand-in for the paper's data: the HiTS DECam warped 4K x 4K patches with
+their variance and mask planes (Sec. 3.1) are not available, so every stack
+here is synthetic noise plus injected point sources rendered with a Gaussian
+PSF (Sec. 2.3 uses a Gaussian PSF approximation; Sec. 4.1 injects sources
+with a Gaussian PSF matched to the search PSF).
+
+Conventions used everywhere in this package:
+  * img, var: float32 [N][H][W]; mask: uint8 [N][H][W], nonzero = bad pixel;
+  * t: float64 [N] in days, ascending; trajectories start at t[0];
+  * psf: float32 [ph][pw], odd sizes, centre at (ph//2, pw//2);
+  * vel: float64 [V][2] = (vx, vy) in pixels/day; x = column, y = row.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from scipy.special import ndtr
+
+SEED_BASE = 1901_02492
+
+
+def seed_for(cfg: int, stream: int) -> int:
+    """Seed of random stream `stream` (0 noise, 1 masks, 2 injections) of workload `cfg`."""
+    return SEED_BASE + 10 * cfg + stream
+
+
+# ---------------------------------------------------------------------------
+# PSF kernels (Sec. 2.1.2: the PSF used for the likelihood images includes the
+# pixel transfer function, i.e. a top-hat pixel convolved with the PSF).
+# ---------------------------------------------------------------------------
+
+def _pixel_integrated_1d(sigma: float, half: int) -> np.ndarray:
+    u = np.arange(-half, half + 1, dtype=np.float64)
+    return ndtr((u + 0.5) / sigma) - ndtr((u - 0.5) / sigma)
+
+
+def psf_gaussian(sigma: float, size: int, integrated: bool = True) -> np.ndarray:
+    """Normalised (unit-sum) Gaussian PSF on an odd `size` x `size` window.
+
+    integrated=True integrates the Gaussian over each unit pixel (the pixel
+    transfer function of Sec. 2.1.2); False samples it at pixel centres.
+    Returned as float32: the float32 values are what both the library and the
+    oracle consume.
+    """
+    if size % 2 != 1:
+        raise ValueError("PSF size must be odd")
+    half = size // 2
+    if integrated:
+        g = _pixel_integrated_1d(sigma, half)
+    else:
+        u = np.arange(-half, half + 1, dtype=np.float64)
+        g = np.exp(-0.5 * (u / sigma) ** 2)
+    k = np.outer(g, g)
+    k /= k.sum()
+    return k.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Velocity grids (Sec. 3.2: a linearly spaced grid of angles x speeds).
+# ---------------------------------------------------------------------------
+
+def velocity_grid_xy(vx_values, vy_values) -> np.ndarray:
+    """Cartesian grid: index j = a * len(vy_values) + b for (vx_values[a], vy_values[b])."""
+    vx = np.asarray(vx_values, dtype=np.float64)
+    vy = np.asarray(vy_values, dtype=np.float64)
+    out = np.empty((vx.size * vy.size, 2), dtype=np.float64)
+    out[:, 0] = np.repeat(vx, vy.size)
+    out[:, 1] = np.tile(vy, vx.size)
+    return out
+
+
+def velocity_grid_polar(speeds, angles) -> np.ndarray:
+    """Speed x angle grid: j = i_s * n_angles + i_theta, v = s (cos theta, sin theta)."""
+    s = np.asarray(speeds, dtype=np.float64)
+    th = np.asarray(angles, dtype=np.float64)
+    ss = np.repeat(s, th.size)
+    tt = np.tile(th, s.size)
+    return np.stack([ss * np.cos(tt), ss * np.sin(tt)], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Source rendering (input synthesis only).
+# ---------------------------------------------------------------------------
+
+def render_point_source(img: np.ndarray, cx: float, cy: float, flux: float,
+                        sigma: float) -> None:
+    """Add a pixel-integrated Gaussian of total `flux` centred at (cx, cy) to img in place."""
+    h, w = img.shape
+    r = int(math.ceil(5.0 * sigma))
+    x0, x1 = int(math.floor(cx)) - r, int(math.floor(cx)) + r + 1
+    y0, y1 = int(math.floor(cy)) - r, int(math.floor(cy)) + r + 1
+    xa, xb = max(x0, 0), min(x1, w)
+    ya, yb = max(y0, 0), min(y1, h)
+    if xa >= xb or ya >= yb:
+        return
+    xs = np.arange(xa, xb, dtype=np.float64)
+    ys = np.arange(ya, yb, dtype=np.float64)
+    gx = ndtr((xs + 0.5 - cx) / sigma) - ndtr((xs - 0.5 - cx) / sigma)
+    gy = ndtr((ys + 0.5 - cy) / sigma) - ndtr((ys - 0.5 - cy) / sigma)
+    img[ya:yb, xa:xb] += (flux * np.outer(gy, gx)).astype(img.dtype)
+
+
+@dataclasses.dataclass
+class Stack:
+    """One synthetic search problem plus the truth it was drawn from."""
+    img: np.ndarray          # float32 [N][H][W]
+    var: np.ndarray          # float32 [N][H][W]
+    mask: np.ndarray         # uint8  [N][H][W]
+    t: np.ndarray            # float64 [N]
+    psf: np.ndarray          # float32 [ph][pw]
+    vel: np.ndarray          # float64 [V][2]
+    k: int                   # results kept per start pixel
+    sources: np.ndarray      # float64 [S][5]: x0, y0, vx, vy, flux
+    name: str = ""
+
+    @property
+    def shape(self):
+        return self.img.shape
+
+    @property
+    def tie(self) -> int:
+        """Trajectory-image evaluations of one full search: N * H * W * V."""
+        n, h, w = self.img.shape
+        return int(n) * int(h) * int(w) * int(self.vel.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# Workloads.
+# ---------------------------------------------------------------------------
+
+def small_stack() -> Stack:
+    """5 images of 64x64 at t = 0..0.2 d, unit noise and variance, 7x7 PSF (sigma 1),
+    one source of flux 50 from (20, 30) moving (40, 25) px/d, an 11x11 velocity
+    grid over [-50, 50] px/d per axis, 5 kept per pixel."""
+    n, h, w = 5, 64, 64
+    rng = np.random.default_rng(seed_for(0, 0))
+    t = np.array([0.0, 0.05, 0.1, 0.15, 0.2], dtype=np.float64)
+    img = rng.standard_normal((n, h, w), dtype=np.float32)
+    var = np.ones((n, h, w), dtype=np.float32)
+    mask = np.zeros((n, h, w), dtype=np.uint8)
+    src = np.array([[20.0, 30.0, 40.0, 25.0, 50.0]])
+    for i in range(n):
+        for x0, y0, vx, vy, f in src:
+            render_point_source(img[i], x0 + vx * t[i], y0 + vy * t[i], f, 1.0)
+    vals = np.arange(-50.0, 50.0 + 1e-9, 10.0)
+    return Stack(img, var, mask, t, psf_gaussian(1.0, 7), velocity_grid_xy(vals, vals),
+                 5, src, name="5x64x64, 121 velocities, K=5")
+
+
+def _smooth_sigma(rng, n, h, w, amp=0.2):
+    """Per-image noise sigma field 1 + amp*sin(2pi(x/W+a))*sin(2pi(y/H+b)), in [0.8, 1.2]."""
+    ph = rng.random((n, 2))
+    xs = np.arange(w, dtype=np.float64) / w
+    ys = np.arange(h, dtype=np.float64) / h
+    out = np.empty((n, h, w), dtype=np.float32)
+    for i in range(n):
+        sx = np.sin(2 * np.pi * (xs + ph[i, 0]))
+        sy = np.sin(2 * np.pi * (ys + ph[i, 1]))
+        out[i] = (1.0 + amp * np.outer(sy, sx)).astype(np.float32)
+    return out
+
+
+def survey_stack(cfg: int = 1, n_nights: int = 3, epochs: int = 5, h: int = 4096,
+                 w: int = 4096, n_src: int = 100, snr=(5.0, 20.0), n_speeds: int = 25,
+                 n_angles: int = 24, k: int = 50, mask_frac: float = 0.01,
+                 psf_sigma: float = 1.5, psf_size: int = 11) -> Stack:
+    """Survey-shaped stack: nights x epochs images 0.06 d apart within a night
+    (Sec. 3.1: ~5 visits per night over three nights), smoothly varying noise
+    sigma in [0.8, 1.2] with var = sigma^2, random 1% masks per image, an
+    11x11 Gaussian PSF (sigma 1.5 px), injected sources at speeds 80-400 px/d
+    within +-0.5 rad of the x axis, and a speed x angle velocity grid over the
+    same ranges.  Defaults: 15 x 4096^2, 600 velocities, K = 50."""
+    n = n_nights * epochs
+    t = np.array([night + 0.06 * e for night in range(n_nights) for e in range(epochs)],
+                 dtype=np.float64)
+    rng_n = np.random.default_rng(seed_for(cfg, 0))
+    rng_m = np.random.default_rng(seed_for(cfg, 1))
+    rng_s = np.random.default_rng(seed_for(cfg, 2))
+    sigma = _smooth_sigma(rng_n, n, h, w)
+    img = np.empty((n, h, w), dtype=np.float32)
+    for i in range(n):
+        img[i] = rng_n.standard_normal((h, w), dtype=np.float32)
+        img[i] *= sigma[i]
+    var = sigma
+    np.square(var, out=var)
+    mask = np.empty((n, h, w), dtype=np.uint8)
+    for i in range(n):
+        mask[i] = rng_m.random((h, w), dtype=np.float32) < mask_frac
+    psf = psf_gaussian(psf_sigma, psf_size)
+    s2 = float(np.sum(psf.astype(np.float64) ** 2))
+    srcs = []
+    for _ in range(n_src):
+        x0 = rng_s.uniform(0, w)
+        y0 = rng_s.uniform(0, h)
+        sp = rng_s.uniform(80.0, 400.0)
+        an = rng_s.uniform(-0.5, 0.5)
+        target = rng_s.uniform(*snr)
+        vx, vy = sp * math.cos(an), sp * math.sin(an)
+        # Flux giving the requested signal-to-noise over the epochs in frame.
+        inv = 0.0
+        for i in range(n):
+            cx, cy = x0 + vx * (t[i] - t[0]), y0 + vy * (t[i] - t[0])
+            if 0 <= cx < w and 0 <= cy < h:
+                inv += s2 / float(var[i, int(cy), int(cx)])
+        flux = target / math.sqrt(inv) if inv > 0 else 0.0
+        for i in range(n):
+            render_point_source(img[i], x0 + vx * (t[i] - t[0]), y0 + vy * (t[i] - t[0]),
+                                flux, psf_sigma)
+        srcs.append((x0, y0, vx, vy, flux))
+    speeds = np.linspace(80.0, 400.0, n_speeds)
+    angles = np.linspace(-0.5, 0.5, n_angles)
+    return Stack(img, var, mask, t, psf, velocity_grid_polar(speeds, angles), k,
+                 np.array(srcs, dtype=np.float64),
+                 name=f"{n}x{h}x{w}, {n_speeds * n_angles} velocities, K={k}")
+
+
+def random_stack(seed: int, n: int, h: int, w: int, n_vel: int, k: int,
+                 psf_size: int = 5, psf_sigma: float = 1.0, mask_frac: float = 0.05,
+                 vmax: float = 40.0, tmax: float = 1.0) -> Stack:
+    """Small randomized stack for parity sweeps: random times, noise, variance
+    and masks; velocities drawn uniformly in [-vmax, vmax]^2 so tracks leave
+    the frame on every side."""
+    rng = np.random.default_rng(SEED_BASE + 7919 * seed)
+    t = np.sort(rng.uniform(0.0, tmax, size=n))
+    t[0] = 0.0
+    img = rng.standard_normal((n, h, w), dtype=np.float32)
+    var = rng.uniform(0.5, 2.0, size=(n, h, w)).astype(np.float32)
+    mask = (rng.random((n, h, w)) < mask_frac).astype(np.uint8)
+    vel = rng.uniform(-vmax, vmax, size=(n_vel, 2))
+    src = []
+    if h > 8 and w > 8:
+        x0, y0 = rng.uniform(2, w - 2), rng.uniform(2, h - 2)
+        vx, vy = vel[0]
+        for i in range(n):
+            render_point_source(img[i], x0 + vx * t[i], y0 + vy * t[i], 20.0, psf_sigma)
+        src.append((x0, y0, vx, vy, 20.0))
+    return Stack(img, var, mask, t, psf_gaussian(psf_sigma, psf_size), vel, k,
+                 np.array(src, dtype=np.float64).reshape(-1, 5), name=f"random{seed}")

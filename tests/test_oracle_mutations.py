@@ -1,0 +1,84 @@
+"""Planted mistakes in the oracle (on the CPU) must be caught by its pins.
+
+Each case swaps one oracle step for a plausible wrong version and re-runs a
+pin from test_oracle_pins.py, which must then fail.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.core as core
+from tests import test_oracle_pins as pins
+
+
+def _patch(monkeypatch, name, fn):
+    """Replace an oracle step both where the pins call it and where the oracle does."""
+    monkeypatch.setattr(core, name, fn)
+    monkeypatch.setattr(oracle, name, fn, raising=False)
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_convolution_instead_of_correlation_is_caught(monkeypatch):
+    orig = core._correlate_zero
+    _patch(monkeypatch, "_correlate_zero", lambda p, k: orig(p, k[::-1, ::-1]))
+    assert _fails(pins.test_planes_equal_scipy_correlate_asymmetric_psf)
+
+
+def test_round_half_even_is_caught(monkeypatch):
+    def disp_rint(t, vel):
+        t = np.asarray(t, np.float64)
+        vel = np.asarray(vel, np.float64).reshape(-1, 2)
+        return np.rint(vel[:, None, :] * (t - t[0])[None, :, None]).astype(np.int64)
+    _patch(monkeypatch, "displacements", disp_rint)
+    assert _fails(pins.test_displacement_half_ties, -30, 0.05, -1)
+    assert _fails(pins.test_displacements_equal_exact_rationals_on_small_grid)
+
+
+def test_swapped_axes_are_caught(monkeypatch):
+    orig = core.displacements
+    _patch(monkeypatch, "displacements", lambda t, v: orig(t, v)[:, :, ::-1])
+    assert _fails(pins.test_search_equals_brute_force, 0, 3, 7, 9, 6, 3)
+
+
+def test_invalid_centre_not_zeroed_is_caught(monkeypatch):
+    orig = core.psi_phi
+
+    def leaky(img, var, mask, psf):
+        psi, phi, ok = orig(img, var, None, psf)     # mask ignored
+        return psi, phi, ok
+    _patch(monkeypatch, "psi_phi", leaky)
+    assert _fails(pins.test_masking_an_image_equals_dropping_it)
+
+
+def test_dropped_sqrt_is_caught(monkeypatch):
+    def bad_scores(Psi, Phi):
+        pos = Phi > 0
+        safe = np.where(pos, Phi, 1.0)
+        return np.where(pos, Psi / safe, -np.inf), np.where(pos, Psi / safe, 0.0)
+    _patch(monkeypatch, "scores", bad_scores)
+    assert _fails(pins.test_closed_form_point_source, 1.0, 7, 5, 50.0, 1.0)
+    assert _fails(pins.test_noise_only_nu_is_standard_normal)
+
+
+def test_unweighted_phi_is_caught(monkeypatch):
+    # phi built with T instead of T^2.
+    orig = core._correlate_zero
+    calls = {"n": 0}
+
+    def corr(p, k):
+        calls["n"] += 1
+        return orig(p, np.sqrt(k) if calls["n"] % 2 == 0 else k)
+    _patch(monkeypatch, "_correlate_zero", corr)
+    assert _fails(pins.test_closed_form_point_source, 1.5, 11, 15, 12.5, 0.8)
+
+
+def test_tie_break_by_descending_index_is_caught(monkeypatch):
+    _patch(monkeypatch, "rank_topk", lambda nu, k: (nu.shape[0] - 1 - np.argsort(-nu[::-1], axis=0, kind="stable"))[:k])
+    assert _fails(pins.test_rank_topk_equals_sorted_with_ties)

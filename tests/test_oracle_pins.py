@@ -1,0 +1,368 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test ties the oracle to something other than itself: a library routine
+the definition reduces to, exact rational arithmetic, a literal-loop brute
+force, a closed form, a statistical invariant, or a special case.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import ndimage, stats
+
+import oracle
+from paper_1901_02492_amd import synth
+from tests import brute_ref
+
+
+def _rand_stack(seed, n, h, w, mask_frac=0.1):
+    rng = np.random.default_rng(seed)
+    img = rng.standard_normal((n, h, w)).astype(np.float32)
+    var = rng.uniform(0.5, 2.0, (n, h, w)).astype(np.float32)
+    mask = (rng.random((n, h, w)) < mask_frac).astype(np.uint8)
+    return img, var, mask
+
+
+# --- planes: Sec. 2.1.5 defines psi as the weighted cross-correlation -------
+
+def test_planes_equal_scipy_correlate_asymmetric_psf():
+    img, var, mask = _rand_stack(1, 3, 23, 31)
+    img[1, 4, 7] = np.nan          # non-finite image -> invalid
+    var[2, 10, 3] = 0.0            # non-positive variance -> invalid
+    rng = np.random.default_rng(5)
+    psf = rng.uniform(0.0, 1.0, (5, 7)).astype(np.float32)   # asymmetric on purpose
+    psi, phi, ok = oracle.psi_phi(img, var, mask, psf)
+    valid = (mask == 0) & np.isfinite(img) & np.isfinite(var) & (var > 0)
+    assert np.array_equal(ok, valid)
+    t = psf.astype(np.float64)
+    for i in range(3):
+        a = np.where(valid[i], img[i].astype(np.float64) / np.where(valid[i], var[i], 1.0), 0.0)
+        w = np.where(valid[i], 1.0 / np.where(valid[i], var[i].astype(np.float64), 1.0), 0.0)
+        ref_psi = ndimage.correlate(a, t, mode="constant", cval=0.0)
+        ref_phi = ndimage.correlate(w, t * t, mode="constant", cval=0.0)
+        ref_psi[~valid[i]] = 0.0
+        ref_phi[~valid[i]] = 0.0
+        np.testing.assert_allclose(psi[i], ref_psi, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(phi[i], ref_phi, rtol=1e-12, atol=1e-12)
+
+
+def test_delta_image_reproduces_reflected_psf():
+    # A unit impulse at (y0, x0) with unit variance: psi(y0 - du, x0 - dv) = T(c + du, c + dv)
+    # read back through the cross-correlation, i.e. the PSF rotated by 180 degrees
+    # around the impulse.
+    h = w = 15
+    img = np.zeros((1, h, w), np.float32)
+    img[0, 7, 6] = 1.0
+    var = np.ones_like(img)
+    psf = np.arange(1, 26, dtype=np.float32).reshape(5, 5)
+    psi, _, _ = oracle.psi_phi(img, var, None, psf)
+    for u in range(5):
+        for v in range(5):
+            assert psi[0, 7 - (u - 2), 6 - (v - 2)] == psf[u, v]
+
+
+def test_planes_equal_brute_force():
+    img, var, mask = _rand_stack(2, 2, 9, 11, mask_frac=0.2)
+    psf = synth.psf_gaussian(1.0, 5)
+    psi, phi, ok = oracle.psi_phi(img, var, mask, psf)
+    bpsi, bphi, bok = brute_ref.planes(img, var, mask, psf)
+    np.testing.assert_allclose(psi, np.array(bpsi), rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(phi, np.array(bphi), rtol=1e-13, atol=1e-14)
+    assert np.array_equal(ok, np.array(bok))
+
+
+# --- displacements: floor(v * tau + 0.5) ------------------------------------
+
+def _exact_round(v, tau):
+    """floor(x + 1/2) of the exact rational product of the decimal literals."""
+    x = Fraction(str(v)) * Fraction(str(tau))
+    return math.floor(x + Fraction(1, 2))
+
+
+def test_displacements_equal_exact_rationals_on_small_grid():
+    # 5 images at 0, 0.05, 0.1, 0.15, 0.2 d and an 11x11 grid over [-50, 50]:
+    # the FP64 multiply-add-floor agrees with exact decimal arithmetic everywhere,
+    # including the 12 exact half-integer products.
+    s = synth.small_stack()
+    d = oracle.displacements(s.t, s.vel)
+    vals = [-50 + 10 * a for a in range(11)]
+    ts = ["0", "0.05", "0.1", "0.15", "0.2"]
+    halves = 0
+    for j, (vx, vy) in enumerate(s.vel):
+        for i, tl in enumerate(ts):
+            assert d[j, i, 0] == _exact_round(int(vx), tl)
+            assert d[j, i, 1] == _exact_round(int(vy), tl)
+    for v in vals:
+        for tl in ts:
+            if (Fraction(v) * Fraction(tl)).denominator == 2:
+                halves += 1
+    assert halves == 12
+
+
+@pytest.mark.parametrize("v,tau,expect", [
+    (-50, 0.05, -2),   # -2.5 -> -2: halves round toward +inf, not to even (-2) by luck
+    (-30, 0.05, -1),   # -1.5 -> -1 (rint and C round give -2)
+    (-10, 0.05, 0),    # -0.5 -> 0 (C round gives -1)
+    (30, 0.05, 2),     # 1.5 -> 2
+    (30, 0.15, 5),     # 4.5 -> 5 (rint gives 4)
+    (-50, 0.15, -7),   # -7.5 -> -7; the FP32 product -7.5000005 would give -8
+    (10, 0.05, 1),     # 0.5 -> 1
+])
+def test_displacement_half_ties(v, tau, expect):
+    t = np.array([0.0, tau])
+    d = oracle.displacements(t, np.array([[v, v]], dtype=np.float64))
+    assert d[0, 1, 0] == expect and d[0, 1, 1] == expect
+    assert d[0, 0, 0] == 0
+
+
+def test_displacements_fp32_would_differ():
+    # Why the table is computed in double: in float32 the same rule moves a pixel.
+    v, tau = np.float32(-50.0), np.float32(0.15)
+    assert math.floor(float(np.float32(v * tau) + np.float32(0.5))) == -8
+    assert oracle.displacements(np.array([0.0, 0.15]), np.array([[-50.0, 0.0]]))[0, 1, 0] == -7
+
+
+# --- full search against brute force ----------------------------------------
+
+@pytest.mark.parametrize("seed,n,h,w,nv,k", [(0, 3, 7, 9, 6, 3), (1, 4, 12, 10, 9, 9),
+                                              (2, 1, 5, 12, 4, 1), (3, 2, 11, 5, 7, 4)])
+def test_search_equals_brute_force(seed, n, h, w, nv, k):
+    rng = np.random.default_rng(100 + seed)
+    img, var, mask = _rand_stack(seed, n, h, w, mask_frac=0.15)
+    t = np.sort(rng.uniform(0, 1, n))
+    t[0] = 0.0
+    vel = rng.uniform(-12, 12, (nv, 2))
+    vel[0] = (0.0, 0.0)
+    psf = synth.psf_gaussian(0.8, 3)
+    r = oracle.search(img, var, mask, t, psf, vel, k)
+    traj, top = brute_ref.search(img, var, mask, t, psf, vel, k)
+    for y in range(h):
+        for x in range(w):
+            for j in range(nv):
+                P, F, c, nu, al = traj[(y, x, j)]
+                assert r["all_nobs"][j, y, x] == c
+                if math.isinf(nu):
+                    assert np.isneginf(r["all_nu"][j, y, x]) and r["all_alpha"][j, y, x] == 0
+                else:
+                    assert abs(r["all_nu"][j, y, x] - nu) <= 1e-12 * max(1, abs(nu))
+                    assert abs(r["all_alpha"][j, y, x] - al) <= 1e-12 * max(1, abs(al))
+            assert list(r["vel"][y, x]) == top[(y, x)]
+
+
+# --- closed form for a noise-free point source (Sec. 2.1.5) ------------------
+
+@pytest.mark.parametrize("sigma,size,n,flux,noise", [(1.0, 7, 5, 50.0, 1.0),
+                                                     (1.5, 11, 15, 12.5, 0.8),
+                                                     (1.0, 7, 3, 7.0, 2.0)])
+def test_closed_form_point_source(sigma, size, n, flux, noise):
+    # Source = flux * T centred on an integer pixel moving one grid velocity
+    # with integer steps; constant variance; kernel fully inside the frame.
+    # Then psi(y_i) = flux * S2 / s^2 and phi(y_i) = S2 / s^2 with S2 = sum T^2,
+    # so alpha_ML = flux exactly and nu = flux * sqrt(n * S2) / s.
+    h, w = 48, 64
+    psf = synth.psf_gaussian(sigma, size)
+    T = psf.astype(np.float64)
+    S2 = float((T * T).sum())
+    c = size // 2
+    t = np.arange(n, dtype=np.float64) * 0.25
+    v = (8.0, -4.0)
+    x0, y0 = 20, 30
+    img = np.zeros((n, h, w), np.float64)
+    for i in range(n):
+        xi, yi = x0 + int(v[0] * t[i]), y0 + int(v[1] * t[i])
+        img[i, yi - c:yi + c + 1, xi - c:xi + c + 1] = flux * T
+    var = np.full((n, h, w), noise ** 2)
+    vel = np.array([[0.0, 0.0], v, [4.0, 4.0]])
+    r = oracle.search(img, var, None, t, psf, vel, 3)
+    Psi_expect = n * flux * S2 / noise ** 2
+    Phi_expect = n * S2 / noise ** 2
+    nu_expect = flux * math.sqrt(n * S2) / noise
+    assert r["vel"][y0, x0, 0] == 1
+    assert abs(r["all_Phi"][1, y0, x0] - Phi_expect) <= 1e-12 * Phi_expect
+    assert abs(r["all_alpha"][1, y0, x0] - flux) <= 1e-12 * flux
+    assert abs(r["all_nu"][1, y0, x0] - nu_expect) <= 1e-12 * nu_expect
+    assert abs(r["all_alpha"][1, y0, x0] * r["all_Phi"][1, y0, x0] - Psi_expect) <= 1e-11 * Psi_expect
+
+
+def test_closed_form_small_workload_values():
+    # 5 images, unit noise, pixel-integrated Gaussian sigma 1 on 7x7, flux 50:
+    # S2 = 0.0735312421..., nu = 50 * sqrt(5 * S2) = 30.3173304... (the PSF is
+    # stored in float32, which moves the last digits by ~1e-7).
+    psf = synth.psf_gaussian(1.0, 7).astype(np.float64)
+    S2 = float((psf ** 2).sum())
+    assert abs(S2 - 0.0735312421) < 1e-9
+    assert abs(50 * math.sqrt(5 * S2) - 30.31733045) < 1e-6
+
+
+# --- noise invariant: nu ~ N(0, 1) for any fixed trajectory (Sec. 2.1.5) -------
+
+def test_noise_only_nu_is_standard_normal():
+    n, h, w = 4, 256, 256
+    rng = np.random.default_rng(77)
+    sig = rng.uniform(0.7, 1.4, (n, h, w))
+    img = (sig * rng.standard_normal((n, h, w))).astype(np.float32)
+    var = (sig ** 2).astype(np.float32)
+    mask = (rng.random((n, h, w)) < 0.02).astype(np.uint8)
+    t = np.array([0.0, 0.3, 0.7, 1.1])
+    vel = np.array([[0.0, 0.0], [13.0, -7.0], [-21.0, 5.5]])
+    psf = synth.psf_gaussian(1.0, 5)
+    r = oracle.search(img, var, mask, t, psf, vel, 3)
+    # One velocity at a time and start pixels 8 apart: every image's visited
+    # pixels are then 8 apart (> the 5-pixel PSF), so the samples are independent.
+    for j in range(3):
+        samp = r["all_nu"][j, 20:236:8, 20:236:8].ravel()
+        samp = samp[np.isfinite(samp)]
+        m = samp.size
+        assert m > 700
+        assert abs(samp.mean()) < 5 / math.sqrt(m)
+        assert abs(samp.std() - 1) < 5 / math.sqrt(2 * m)
+        assert stats.kstest(samp, "norm").pvalue > 1e-3
+
+
+def test_alpha_is_unbiased_over_noise():
+    n, h, w = 3, 24, 24
+    psf = synth.psf_gaussian(1.0, 5)
+    T = psf.astype(np.float64)
+    t = np.array([0.0, 0.5, 1.0])
+    vel = np.array([[4.0, 2.0]])
+    flux = 3.0
+    rng = np.random.default_rng(11)
+    est = []
+    for _ in range(300):
+        img = rng.standard_normal((n, h, w))
+        for i in range(n):
+            yi, xi = 10 + int(2 * t[i]), 10 + int(4 * t[i])
+            img[i, yi - 2:yi + 3, xi - 2:xi + 3] += flux * T
+        r = oracle.search_pixels(img, np.ones_like(img), None, t, psf, vel, 1, [10], [10])
+        est.append(r["all_alpha"][0, 0])
+    est = np.array(est)
+    sd = 1 / math.sqrt(n * float((T * T).sum()))
+    assert abs(est.mean() - flux) < 5 * sd / math.sqrt(est.size)
+    assert abs(est.std() - sd) < 0.15 * sd
+
+
+# --- special cases -----------------------------------------------------------
+
+def test_zero_velocity_is_static_coadd():
+    img, var, mask = _rand_stack(3, 4, 16, 20)
+    psf = synth.psf_gaussian(1.0, 5)
+    t = np.array([0.0, 0.1, 0.4, 0.9])
+    r = oracle.search(img, var, mask, t, psf, np.array([[0.0, 0.0], [5.0, 5.0]]), 1)
+    psi, phi, ok = oracle.psi_phi(img, var, mask, psf)
+    Psi, Phi = psi.sum(0), phi.sum(0)
+    nu, al = oracle.scores(Psi, Phi)
+    np.testing.assert_allclose(r["all_nu"][0], nu, rtol=1e-13, atol=1e-13)
+    assert np.array_equal(r["all_nobs"][0], ok.sum(0))
+
+
+def test_single_image_is_matched_filter():
+    img, var, mask = _rand_stack(4, 1, 18, 22)
+    psf = synth.psf_gaussian(1.2, 7)
+    psi, phi, ok = oracle.psi_phi(img, var, mask, psf)
+    vel = np.array([[3.0, 1.0], [-9.0, 2.0]])
+    r = oracle.search(img, var, mask, np.array([0.0]), psf, vel, 2)
+    mf = np.where(phi > 0, psi / np.sqrt(np.where(phi > 0, phi, 1)), -np.inf)
+    for j in range(2):
+        np.testing.assert_allclose(r["all_nu"][j], mf[0], rtol=1e-14)
+
+
+def test_masking_an_image_equals_dropping_it():
+    img, var, mask = _rand_stack(5, 4, 20, 20, mask_frac=0.05)
+    psf = synth.psf_gaussian(1.0, 5)
+    t = np.array([0.0, 0.2, 0.5, 0.8])
+    vel = np.random.default_rng(3).uniform(-10, 10, (7, 2))
+    m2 = mask.copy()
+    m2[2] = 1
+    a = oracle.search(img, var, m2, t, psf, vel, 7)
+    keep = [0, 1, 3]
+    b = oracle.search(img[keep], var[keep], mask[keep], t[keep], psf, vel, 7)
+    np.testing.assert_allclose(a["all_nu"], b["all_nu"], rtol=1e-13, atol=1e-13)
+    assert np.array_equal(a["all_nobs"], b["all_nobs"])
+    assert np.array_equal(a["vel"], b["vel"])
+
+
+def test_translation_moves_interior_results():
+    n, h, w = 3, 40, 40
+    img, var, mask = _rand_stack(6, n, h, w, mask_frac=0.0)
+    psf = synth.psf_gaussian(1.0, 5)
+    t = np.array([0.0, 0.25, 0.5])
+    vel = np.array([[4.0, 0.0], [0.0, -4.0], [6.0, 6.0]])
+    sy, sx = 3, 5
+    img2 = np.zeros_like(img)
+    var2 = np.ones_like(var)
+    img2[:, sy:, sx:] = img[:, :h - sy, :w - sx]
+    var2[:, sy:, sx:] = var[:, :h - sy, :w - sx]
+    a = oracle.search(img, var, None, t, psf, vel, 3)
+    b = oracle.search(img2, var2, None, t, psf, vel, 3)
+    # Start pixels whose trajectories and PSF footprints stay well inside both frames.
+    ys, xs = slice(8, 25), slice(8, 25)
+    ys2, xs2 = slice(8 + sy, 25 + sy), slice(8 + sx, 25 + sx)
+    np.testing.assert_allclose(a["all_nu"][:, ys, xs], b["all_nu"][:, ys2, xs2], rtol=1e-12)
+
+
+def test_time_offset_changes_nothing():
+    img, var, mask = _rand_stack(7, 3, 16, 16)
+    psf = synth.psf_gaussian(1.0, 3)
+    t = np.array([0.0, 0.25, 0.625])          # exact binary fractions
+    vel = np.array([[8.0, -4.0], [2.0, 2.0], [-6.0, 1.0]])
+    a = oracle.search(img, var, mask, t, psf, vel, 3)
+    b = oracle.search(img, var, mask, t + 1024.0, psf, vel, 3)
+    assert np.array_equal(a["all_nu"], b["all_nu"])
+
+
+def test_depth_grows_as_sqrt_n():
+    # Same noise-free source in N identical images: nu scales as sqrt(N) (Sec. 1).
+    psf = synth.psf_gaussian(1.0, 5)
+    T = psf.astype(np.float64)
+    base = np.zeros((16, 16))
+    base[6:11, 6:11] = 9.0 * T
+    vel = np.array([[0.0, 0.0]])
+    nus = []
+    for n in (1, 4, 9, 16):
+        img = np.repeat(base[None], n, axis=0)
+        r = oracle.search(img, np.ones_like(img), None, np.arange(n) * 0.1, psf, vel, 1)
+        nus.append(r["all_nu"][0, 8, 8])
+    for n, v in zip((1, 4, 9, 16), nus):
+        assert abs(v - math.sqrt(n) * nus[0]) <= 1e-12 * v
+
+
+def test_no_valid_observation_scores_minus_inf():
+    img, var, mask = _rand_stack(8, 2, 6, 6)
+    mask[:] = 1
+    r = oracle.search(img, var, mask, np.array([0.0, 1.0]), synth.psf_gaussian(1.0, 3),
+                      np.array([[1.0, 0.0], [0.0, 0.0]]), 2)
+    assert np.all(np.isneginf(r["nu"])) and np.all(r["alpha"] == 0) and np.all(r["nobs"] == 0)
+    assert np.array_equal(r["vel"][..., 0], np.zeros((6, 6)))   # ties -> lowest index first
+
+
+def test_rank_topk_equals_sorted_with_ties():
+    rng = np.random.default_rng(9)
+    nu = rng.integers(-3, 4, size=(40, 5)).astype(np.float64)
+    nu[rng.random(nu.shape) < 0.1] = -np.inf
+    order = oracle.rank_topk(nu, 12)
+    for p in range(5):
+        ref = sorted(range(40), key=lambda j: (-nu[j, p], j))[:12]
+        assert list(order[:, p]) == ref
+
+
+def test_row_band_and_pixel_helpers_agree_with_full_search():
+    s = synth.random_stack(3, n=4, h=30, w=26, n_vel=9, k=4, psf_size=5)
+    full = oracle.search(s.img, s.var, s.mask, s.t, s.psf, s.vel, s.k)
+    band = oracle.search_rows(s.img, s.var, s.mask, s.t, s.psf, s.vel, s.k, 11, 19)
+    assert np.array_equal(band["vel"], full["vel"][11:19])
+    np.testing.assert_allclose(band["all_nu"], full["all_nu"][:, 11:19], rtol=1e-13)
+    ys = np.array([0, 29, 15, 3])
+    xs = np.array([0, 25, 12, 20])
+    pix = oracle.search_pixels(s.img, s.var, s.mask, s.t, s.psf, s.vel, s.k, ys, xs)
+    assert np.array_equal(pix["vel"], full["vel"][ys, xs])
+    np.testing.assert_allclose(pix["all_nu"], full["all_nu"][:, ys, xs], rtol=1e-13)
+
+
+def test_small_workload_top_result_at_true_track():
+    # The injected source starts at (20, 30) with velocity (40, 25) px/d; the
+    # nearest grid velocity reached at every epoch is (40, 20).
+    s = synth.small_stack()
+    r = oracle.search(s.img, s.var, s.mask, s.t, s.psf, s.vel, s.k)
+    assert tuple(s.vel[r["vel"][30, 20, 0]]) == (40.0, 20.0)
+    assert r["nu"][30, 20, 0] > 20
