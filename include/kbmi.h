@@ -1,0 +1,186 @@
+/*
+ * kbmi.h - C ABI of the maximum-likelihood shift-and-stack trajectory search
+ * (Whidden et al. 2019, "Fast algorithms for slow moving asteroids") on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The search has three device stages and one host helper:
+ *   kb_make_psi_phi   likelihood images psi, phi of every image    (Sec. 2.1.5)
+ *   kb_search         coadd psi, phi along every linear trajectory  (Sec. 2.1.5
+ *                     coadd, Sec. 2.2) and keep the k_cand best per start pixel
+ *   kb_topk           order each start pixel's candidates and keep k
+ *   kb_displacements  the integer pixel offsets every kernel uses   (Sec. 2.2)
+ *
+ * Conventions shared by every call
+ *   - Pixel (x, y) is column x, row y of a row-major [h][w] frame; integer
+ *     coordinates are pixel centres.  Image stacks are [n_img][h][w].
+ *   - Times t[n_img] are in days and must be non-decreasing; trajectories
+ *     start at every pixel of image 0 (the earliest observation, Sec. 3.2).
+ *   - vel[n_vel][2] holds (vx, vy) in pixels per day.  The trajectory of start
+ *     pixel (x0, y0) and velocity j visits, in image i,
+ *         x0 + floor(vx_j * (t_i - t_0) + 0.5),  y0 + floor(vy_j * (t_i - t_0) + 0.5)
+ *     with the product, the sum and the floor evaluated in IEEE double as
+ *     separate operations (halves round toward +infinity).
+ *   - Device pointers are HIP device memory owned by the caller.  Host
+ *     pointers (marked "host") are read before the call returns.  The library
+ *     allocates no device memory and keeps no pointer after a call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     enqueued asynchronously on it; the caller keeps every device buffer
+ *     alive until the stream has passed the work.  Calls on different streams
+ *     may run concurrently.
+ *   - Every argument is checked before anything is enqueued; a failed check
+ *     returns KB_EINVAL or KB_EUNSUPPORTED, writes nothing, and leaves a
+ *     message for kb_last_error().  A failed launch returns KB_EDEVICE.
+ *     Faults inside kernels surface at the caller's next synchronisation.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef KBMI_H
+#define KBMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KB_ABI_VERSION 1
+
+/* Largest per-pixel candidate count kb_search keeps (k_cand). */
+#define KB_MAX_KCAND 64
+/* Largest PSF side length kb_make_psi_phi accepts (odd sizes only). */
+#define KB_MAX_PSF 25
+
+typedef enum kb_status {
+    KB_OK = 0,
+    KB_EINVAL = -1,        /* invalid argument; nothing was enqueued */
+    KB_ENOMEM = -2,        /* caller-provided workspace too small */
+    KB_EDEVICE = -3,       /* HIP runtime error while enqueueing */
+    KB_EUNSUPPORTED = -4   /* valid request outside what this build implements */
+} kb_status;
+
+/* Storage type of the likelihood planes read by kb_search. */
+typedef enum kb_dtype {
+    KB_F32 = 0,            /* float32 (psi, phi) pairs */
+    KB_F16 = 1,            /* scaled IEEE half (psi, phi) pairs */
+    KB_BF16 = 2            /* scaled bfloat16 (psi, phi) pairs */
+} kb_dtype;
+
+/* KB_ABI_VERSION of the loaded library. */
+int kb_abi_version(void);
+
+/* Message describing the last non-OK status returned on this thread
+ * ("" if none).  The pointer stays valid until the next call on this thread. */
+const char *kb_last_error(void);
+
+/*
+ * kb_displacements - integer pixel offsets of every trajectory (Sec. 2.2:
+ * linear trajectories y_i = y_0 + v t_i from the earliest image).
+ *   t     host, float64 [n_img], non-decreasing, finite.
+ *   vel   host, float64 [n_vel][2] (vx, vy) px/day, finite.
+ *   disp  host, int32 [n_vel][n_img][2] out: (dx, dy) per velocity and image,
+ *         exactly as defined in the header comment.
+ * Errors: KB_EINVAL for null pointers, n_img < 1, n_vel < 1, non-finite or
+ * decreasing times, non-finite velocities, or |v * (t_i - t_0)| >= 2^30.
+ * Pure host code; usable without a GPU.
+ */
+kb_status kb_displacements(const double *t, int64_t n_img, const double *vel,
+                           int64_t n_vel, int32_t *disp);
+
+/*
+ * kb_make_psi_phi - per-image likelihood images for a diagonal pixel
+ * covariance (Sec. 2.1.5, the Psi and Phi equations and the masking rule;
+ * Sec. 2.3 computes them on the GPU with one single-pass 2-D kernel):
+ *     valid(p) = mask(p) == 0 and img(p), var(p) finite and var(p) > 0
+ *     psi(y) = sum_u,v valid * img/var (y + (u - cy, v - cx)) * T[u][v]
+ *     phi(y) = sum_u,v valid / var     (y + (u - cy, v - cx)) * T[u][v]^2
+ * a cross-correlation with zero outside the frame, centre (cy, cx) =
+ * (psf_h / 2, psf_w / 2); psi = phi = 0 where valid(y) is false.
+ *   img, var  device, float32 [n_img][h][w].
+ *   mask      device, uint8 [n_img][h][w], nonzero = bad pixel; may be NULL.
+ *   psf       host, float32 [psf_h][psf_w], odd sizes <= KB_MAX_PSF, used as
+ *             given (the caller normalises it).
+ *   psi_phi   device out, float32 [n_img][h][w][2]: (psi, phi) interleaved.
+ *             A valid pixel whose phi is +0 is stored with phi = -0.0 so that
+ *             the stored bit pattern of phi is nonzero exactly at valid pixels.
+ *   lp_dtype  KB_F32 = no low-precision copy.  KB_F16 / KB_BF16 also write
+ *             psi_phi_lp (device, 16-bit [n_img][h][w][2]) holding
+ *             round-to-nearest(value * scale) with per-image, per-plane
+ *             power-of-two scales written to lp_scale (device, float32
+ *             [n_img][2]); not implemented in ABI version 1
+ *             (KB_EUNSUPPORTED).
+ * Errors: KB_EINVAL for null required pointers, n_img < 1, h < 1, w < 1,
+ * even PSF sizes; KB_EUNSUPPORTED for a PSF side > KB_MAX_PSF.
+ */
+kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mask,
+                          int64_t n_img, int64_t h, int64_t w,
+                          const float *psf, int64_t psf_h, int64_t psf_w,
+                          float *psi_phi, int32_t lp_dtype, void *psi_phi_lp,
+                          float *lp_scale, void *stream);
+
+/* Bytes of device workspace kb_search and kb_topk need (the displacement
+ * table plus alignment). */
+size_t kb_search_workspace_bytes(int64_t n_img, int64_t n_vel);
+
+/*
+ * kb_search - exhaustive evaluation of every (start pixel, velocity) pair
+ * (Sec. 2.2) by coadding the likelihood images along the trajectory
+ * (Sec. 2.1.5 coadd equations) and scoring it (Sec. 2.1.5: alpha_ML = Psi/Phi,
+ * nu = Psi/sqrt(Phi)):
+ *     Psi = sum_i psi_i(p_i), Phi = sum_i phi_i(p_i), n_obs = #terms
+ * over the images i in increasing order whose trajectory pixel p_i is inside
+ * the frame and valid; float32 arithmetic.  If Phi > 0: nu = Psi/sqrt(Phi),
+ * alpha = Psi/Phi; otherwise nu = -inf, alpha = 0.  For every start pixel the
+ * k_cand best trajectories in the order (nu descending, velocity index
+ * ascending) are kept.
+ *   planes     device, [n_img][h][w][2] pairs as written by kb_make_psi_phi,
+ *              of type `dtype` (only KB_F32 in ABI version 1).
+ *   lp_scale   device float32 [n_img][2] for 16-bit planes; NULL for KB_F32.
+ *   t, vel     host, as for kb_displacements.
+ *   k_cand     1 <= k_cand <= min(n_vel, KB_MAX_KCAND).
+ *   cand_nu, cand_alpha  device out, float32 [h][w][k_cand].
+ *   cand_vel   device out, int32 [h][w][k_cand]: velocity index j.
+ *   cand_nobs  device out, int16 [h][w][k_cand]: n_obs.
+ *              Each pixel's k_cand entries are the best set; their order
+ *              within a pixel is unspecified (kb_topk orders them).
+ *   workspace  device, >= kb_search_workspace_bytes(n_img, n_vel) bytes,
+ *              256-byte aligned; overwritten.
+ * Limits: n_img <= 32767, n_vel <= 65535, w <= 2^27, h <= 2^31 - 1.
+ * The displacement table is copied host-to-device on `stream`; from pageable
+ * memory that copy may wait for earlier work on the stream.
+ * Errors: KB_EINVAL for bad sizes, pointers or times; KB_ENOMEM for a short
+ * workspace; KB_EUNSUPPORTED for k_cand > KB_MAX_KCAND or 16-bit planes.
+ */
+kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale,
+                    int64_t n_img, int64_t h, int64_t w,
+                    const double *t, const double *vel, int64_t n_vel, int64_t k_cand,
+                    float *cand_nu, float *cand_alpha, int32_t *cand_vel,
+                    int16_t *cand_nobs, void *workspace, size_t workspace_bytes,
+                    void *stream);
+
+/*
+ * kb_topk - final per-pixel selection: order each start pixel's k_cand
+ * candidates by (nu descending, velocity index ascending) and keep the first
+ * k (Sec. 2.2 asks for the trajectories maximising nu).
+ *   psi_phi_f32  device float32 planes [n_img][h][w][2] to re-score every
+ *                candidate from before ordering (used after a 16-bit search),
+ *                or NULL to keep the candidates' scores.  Re-scoring is not
+ *                implemented in ABI version 1 (KB_EUNSUPPORTED).
+ *   t, vel, n_vel, workspace  as for kb_search (used only when re-scoring).
+ *   cand_*       device, as written by kb_search.
+ *   nu, alpha, vel_idx, nobs  device out, [h][w][k] in rank order.
+ * Errors: KB_EINVAL for bad sizes or pointers or k > k_cand; KB_EUNSUPPORTED
+ * for k_cand > KB_MAX_KCAND.
+ */
+kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
+                  const double *t, const double *vel, int64_t n_vel,
+                  const float *cand_nu, const float *cand_alpha,
+                  const int32_t *cand_vel, const int16_t *cand_nobs,
+                  int64_t k_cand, int64_t k,
+                  float *nu, float *alpha, int32_t *vel_idx, int16_t *nobs,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBMI_H */

@@ -1,0 +1,103 @@
+// Host-side part of libkbmi: error reporting, argument checks and the
+// displacement table (Sec. 2.2 linear trajectories started at the earliest
+// image).  Built with -ffp-contract=off: the product v * tau, the sum with 0.5
+// and the floor must stay three separately rounded IEEE double operations so
+// that every offset equals the documented definition bit for bit.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "kbmi_internal.h"
+
+namespace kbmi {
+
+static thread_local std::string g_last_error;
+
+kb_status fail(kb_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static constexpr double kMaxOffset = 1073741824.0;  // 2^30
+
+kb_status check_times_velocities(const double *t, int64_t n_img, const double *vel,
+                                 int64_t n_vel) {
+    if (!t || !vel) return fail(KB_EINVAL, "t and vel must be non-null host arrays");
+    if (n_img < 1) return fail(KB_EINVAL, "n_img must be >= 1 (got %lld)", (long long)n_img);
+    if (n_vel < 1) return fail(KB_EINVAL, "n_vel must be >= 1 (got %lld)", (long long)n_vel);
+    for (int64_t i = 0; i < n_img; ++i) {
+        if (!std::isfinite(t[i])) return fail(KB_EINVAL, "t[%lld] is not finite", (long long)i);
+        if (i > 0 && t[i] < t[i - 1])
+            return fail(KB_EINVAL, "times must be non-decreasing (t[%lld] < t[%lld])",
+                        (long long)i, (long long)(i - 1));
+    }
+    const double tau_max = t[n_img - 1] - t[0];
+    if (!std::isfinite(tau_max)) return fail(KB_EINVAL, "time span is not finite");
+    for (int64_t j = 0; j < n_vel; ++j) {
+        for (int a = 0; a < 2; ++a) {
+            const double v = vel[2 * j + a];
+            if (!std::isfinite(v))
+                return fail(KB_EINVAL, "vel[%lld][%d] is not finite", (long long)j, a);
+            if (std::fabs(v) * tau_max >= kMaxOffset)
+                return fail(KB_EINVAL, "|vel[%lld][%d] * time span| must be < 2^30",
+                            (long long)j, a);
+        }
+    }
+    return KB_OK;
+}
+
+void displacement_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+                        int32_t *disp, int64_t clamp_w, int64_t clamp_h) {
+    const double t0 = t[0];
+    for (int64_t j = 0; j < n_vel; ++j) {
+        for (int64_t i = 0; i < n_img; ++i) {
+            const double tau = t[i] - t0;
+            for (int a = 0; a < 2; ++a) {
+                volatile double prod = vel[2 * j + a] * tau;   // rounded product
+                volatile double shifted = prod + 0.5;          // rounded sum
+                int64_t d = static_cast<int64_t>(std::floor(shifted));
+                const int64_t c = a == 0 ? clamp_w : clamp_h;
+                if (c > 0) d = d < -c ? -c : (d > c ? c : d);
+                disp[(j * n_img + i) * 2 + a] = static_cast<int32_t>(d);
+            }
+        }
+    }
+}
+
+size_t table_bytes(int64_t n_img, int64_t n_vel) {
+    const size_t raw = static_cast<size_t>(n_img) * static_cast<size_t>(n_vel) * 2 * sizeof(int32_t);
+    return (raw + 255) & ~static_cast<size_t>(255);
+}
+
+}  // namespace kbmi
+
+extern "C" {
+
+int kb_abi_version(void) { return KB_ABI_VERSION; }
+
+const char *kb_last_error(void) { return kbmi::g_last_error.c_str(); }
+
+kb_status kb_displacements(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+                           int32_t *disp) {
+    kbmi::clear_error();
+    kb_status st = kbmi::check_times_velocities(t, n_img, vel, n_vel);
+    if (st != KB_OK) return st;
+    if (!disp) return kbmi::fail(KB_EINVAL, "disp must be a non-null host array");
+    kbmi::displacement_table(t, n_img, vel, n_vel, disp, 0, 0);
+    return KB_OK;
+}
+
+size_t kb_search_workspace_bytes(int64_t n_img, int64_t n_vel) {
+    if (n_img < 1 || n_vel < 1) return 0;
+    return kbmi::table_bytes(n_img, n_vel);
+}
+
+}  // extern "C"

@@ -1,0 +1,31 @@
+// Declarations shared by the host-side helpers and the HIP launchers of libkbmi.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "kbmi.h"
+
+namespace kbmi {
+
+// Record the message kb_last_error() returns on this thread; returns `st`.
+kb_status fail(kb_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+// Checks shared by kb_displacements, kb_search and kb_topk: times finite and
+// non-decreasing, velocities finite, every |v * (t_i - t_0)| < 2^30.
+kb_status check_times_velocities(const double *t, int64_t n_img, const double *vel,
+                                 int64_t n_vel);
+
+// Displacement table d[j][i] = (floor(vx_j tau_i + 0.5), floor(vy_j tau_i + 0.5)),
+// tau_i = t_i - t_0, as separate IEEE double operations.  With clamp_w > 0 and
+// clamp_h > 0 each offset is clamped to [-clamp, clamp]: an offset at least a
+// frame extent long puts every start pixel outside the frame either way, and the
+// clamp keeps byte offsets inside 32 bits.  Arguments must already be checked.
+void displacement_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+                        int32_t *disp, int64_t clamp_w, int64_t clamp_h);
+
+// Device workspace layout: the clamped displacement table at offset 0.
+size_t table_bytes(int64_t n_img, int64_t n_vel);
+
+}  // namespace kbmi

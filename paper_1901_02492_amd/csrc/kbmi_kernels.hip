@@ -1,0 +1,494 @@
+// HIP kernels and device entry points of libkbmi (gfx950 / CDNA4, wave64).
+//
+//   psi_phi_kernel   likelihood images psi, phi (Sec. 2.1.5 Psi/Phi equations,
+//                    masking paragraph; Sec. 2.3 single-pass 2-D kernel)
+//   search_kernel    coadd along every linear trajectory and keep the best
+//                    k_cand per start pixel (Sec. 2.1.5 coadd equations and
+//                    nu; Sec. 2.2 exhaustive search over (y0, v))
+//   topk_kernel      order each pixel's candidates and keep k
+//
+// The search is a gather-sum, not a contraction, so nothing here uses MFMA.
+// Each lane owns one start pixel; a wave covers 64 adjacent pixels of one row,
+// so for a fixed (velocity, image) the wave's 64 reads are one contiguous
+// 512-byte run of interleaved (psi, phi) pairs.  Reads go through raw buffer
+// loads whose hardware range check returns zero for columns outside the frame
+// and for rows outside the frame (a zero-length buffer), so out-of-frame
+// positions add exactly +0 and count nothing, without per-lane branches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "kbmi_internal.h"
+
+namespace kbmi {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Raw buffer access (stride 0: an access is out of range when its byte offset
+// is >= the buffer's record count, and then a load returns 0).
+// ---------------------------------------------------------------------------
+constexpr int kBufferFlags = 0x00020000;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kBufferFlags);
+}
+
+// ---------------------------------------------------------------------------
+// Likelihood images.
+// ---------------------------------------------------------------------------
+struct PsfTaps {
+    float t[KB_MAX_PSF * KB_MAX_PSF];
+};
+
+constexpr int PP_TW = 64;       // output tile width (one wave's lanes)
+constexpr int PP_TH = 16;       // output tile height
+constexpr int PP_THREADS = 256; // 4 waves; each thread produces 4 rows of one column
+constexpr int PP_LW = PP_TW + KB_MAX_PSF - 1;
+constexpr int PP_LH = PP_TH + KB_MAX_PSF - 1;
+
+__global__ __launch_bounds__(PP_THREADS) void psi_phi_kernel(
+    const float *__restrict__ img, const float *__restrict__ var,
+    const uint8_t *__restrict__ mask, int h, int w, int ph, int pw, PsfTaps psf,
+    float2 *__restrict__ out) {
+    __shared__ float s_a[PP_LH * PP_LW];
+    __shared__ float s_w[PP_LH * PP_LW];
+    __shared__ uint8_t s_ok[PP_LH * PP_LW];
+
+    const int i = blockIdx.z;
+    const int tx0 = blockIdx.x * PP_TW;
+    const int ty0 = blockIdx.y * PP_TH;
+    const int cy = ph / 2, cx = pw / 2;
+    const int lh = PP_TH + ph - 1, lw = PP_TW + pw - 1;
+    const size_t plane = (size_t)i * (size_t)h * (size_t)w;
+
+    // Stage a = valid * img / var and w = valid / var for the tile plus halo.
+    for (int idx = threadIdx.x; idx < lh * lw; idx += PP_THREADS) {
+        const int ly = idx / lw, lx = idx - ly * lw;
+        const int gy = ty0 + ly - cy, gx = tx0 + lx - cx;
+        float a = 0.f, wt = 0.f;
+        uint8_t ok = 0;
+        if (gy >= 0 && gy < h && gx >= 0 && gx < w) {
+            const size_t p = plane + (size_t)gy * w + gx;
+            const float im = img[p], vr = var[p];
+            const bool good = (mask == nullptr || mask[p] == 0) && isfinite(im) &&
+                              isfinite(vr) && vr > 0.f;
+            if (good) {
+                wt = 1.0f / vr;
+                a = im / vr;
+                ok = 1;
+            }
+        }
+        s_a[ly * PP_LW + lx] = a;
+        s_w[ly * PP_LW + lx] = wt;
+        s_ok[ly * PP_LW + lx] = ok;
+    }
+    __syncthreads();
+
+    const int lx = threadIdx.x & (PP_TW - 1);
+    const int ly0 = threadIdx.x / PP_TW;   // rows ly0, ly0 + 4, ly0 + 8, ly0 + 12
+    float ps[4] = {0.f, 0.f, 0.f, 0.f}, pf[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < ph; ++u) {
+        for (int v = 0; v < pw; ++v) {
+            const float tv = psf.t[u * pw + v];
+            const float t2 = tv * tv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = (ly0 + 4 * r + u) * PP_LW + lx + v;
+                ps[r] = fmaf(s_a[o], tv, ps[r]);
+                pf[r] = fmaf(s_w[o], t2, pf[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gy = ty0 + ly0 + 4 * r, gx = tx0 + lx;
+        if (gy < h && gx < w) {
+            float2 res = make_float2(0.f, 0.f);
+            if (s_ok[(ly0 + 4 * r + cy) * PP_LW + lx + cx]) {
+                // phi >= 0 always; a valid pixel keeps a nonzero bit pattern.
+                res = make_float2(ps[r], pf[r] > 0.f ? pf[r] : -0.0f);
+            }
+            out[plane + (size_t)gy * w + gx] = res;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Candidate keys.  A candidate is ordered by (nu descending, j ascending); the
+// 64-bit key (order-preserving bits of nu) << 32 | (0xFFFF - j) << 16 | n_obs
+// compares the same way as unsigned integers.  n_obs never decides an order
+// because j is unique within a pixel.  Key 0 is below every real candidate
+// (nu = -inf maps to 0x007FFFFF) and marks an empty slot.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t nu_order_bits(float nu) {
+    uint32_t u = __float_as_uint(nu);
+    if (u == 0x80000000u) u = 0u;   // -0 ranks equal to +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ inline float nu_from_order_bits(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+__device__ inline uint64_t make_key(float nu, int j, uint32_t nobs) {
+    return ((uint64_t)nu_order_bits(nu) << 32) |
+           (uint64_t)(((uint32_t)(0xFFFF - j) << 16) | (nobs & 0xFFFFu));
+}
+
+// Scores of one trajectory (Sec. 2.1.5: alpha_ML = Psi / Phi, nu = Psi / sqrt(Phi)).
+__device__ inline void score(float P, float F, float &nu, float &alpha) {
+    if (F > 0.f) {
+        nu = P / sqrtf(F);
+        alpha = P / F;
+    } else {
+        nu = -INFINITY;
+        alpha = 0.f;
+    }
+}
+
+// Start-pixel tiles: one wave = 64 adjacent pixels of one row.  Tiles are
+// enumerated in strips `strip` tiles wide (all rows of a strip, then the next
+// strip) so that consecutive workgroups cover a compact 2-D patch, and the
+// workgroup index is remapped so that each of the 8 XCDs (which receive
+// workgroups round-robin) walks one contiguous range of that order and its
+// L2 sees neighbouring patches.
+struct TileMap {
+    int nseg;     // tiles per row
+    int h;        // rows
+    int strip;    // tiles per strip
+    int nblocks;  // nseg * h
+
+    __device__ inline void map(int b, int &row, int &seg) const {
+        const int xcd = b & 7, k = b >> 3;
+        const int q = nblocks >> 3, r = nblocks & 7;
+        const int t = xcd * q + (xcd < r ? xcd : r) + k;
+        const int fs = nseg / strip;
+        const int full = fs * h * strip;
+        if (t < full) {
+            const int s = t / (h * strip);
+            const int rem = t - s * h * strip;
+            row = rem / strip;
+            seg = s * strip + (rem - (rem / strip) * strip);
+        } else {
+            const int rw = nseg - fs * strip;
+            const int rem = t - full;
+            row = rem / rw;
+            seg = fs * strip + (rem - (rem / rw) * rw);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Trajectory search.  KM = register list length (>= k_cand), NB = images whose
+// loads are issued together before they are summed in image order.
+// ---------------------------------------------------------------------------
+template <int KM, int NB>
+__global__ __launch_bounds__(64) void search_kernel(
+    const float2 *__restrict__ planes, int n_img, int h, int w,
+    const int2 *__restrict__ disp, int n_vel, int k_cand, TileMap tiles,
+    float *__restrict__ cand_nu, float *__restrict__ cand_alpha,
+    int32_t *__restrict__ cand_vel, int16_t *__restrict__ cand_nobs) {
+    int row, seg;
+    tiles.map(blockIdx.x, row, seg);
+    const int x0 = seg * 64 + (int)threadIdx.x;
+    const uint32_t row_bytes = (uint32_t)w * 8u;
+    const size_t img_stride = (size_t)h * (size_t)w;
+
+    uint64_t key[KM];
+    float al[KM];
+#pragma unroll
+    for (int s = 0; s < KM; ++s) {
+        key[s] = 0;
+        al[s] = 0.f;
+    }
+
+    for (int j = 0; j < n_vel; ++j) {
+        const int2 *dj = disp + (size_t)j * n_img;
+        float P = 0.f, F = 0.f;
+        uint32_t cnt = 0;
+        for (int i0 = 0; i0 < n_img; i0 += NB) {
+            u32x2 v[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = i0 + b;
+                if (i < n_img) {
+                    const int2 d = dj[i];
+                    const int yy = row + d.y;
+                    const bool in_rows = (unsigned)yy < (unsigned)h;
+                    const float2 *base = planes + (size_t)i * img_stride +
+                                         (size_t)(in_rows ? yy : 0) * (size_t)w;
+                    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base, in_rows ? row_bytes : 0u);
+                    v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + d.x) * 8, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (i0 + b < n_img) {
+                    P += __uint_as_float(v[b].x);
+                    F += __uint_as_float(v[b].y);
+                    cnt += v[b].y != 0u;
+                }
+            }
+        }
+        float nu, a;
+        score(P, F, nu, a);
+        uint64_t nk = make_key(nu, j, cnt);
+        if (nk > key[KM - 1]) {
+            // Insert into the descending list; the old last entry drops out.
+#pragma unroll
+            for (int s = 0; s < KM; ++s) {
+                const bool c = nk > key[s];
+                const uint64_t tk = c ? key[s] : nk;
+                key[s] = c ? nk : key[s];
+                nk = tk;
+                const float ta = c ? al[s] : a;
+                al[s] = c ? a : al[s];
+                a = ta;
+            }
+        }
+    }
+
+    if (x0 < w) {
+        const size_t o = ((size_t)row * (size_t)w + (size_t)x0) * (size_t)k_cand;
+#pragma unroll
+        for (int s = 0; s < KM; ++s) {
+            if (s < k_cand) {
+                const uint32_t lo = (uint32_t)key[s];
+                cand_nu[o + s] = nu_from_order_bits((uint32_t)(key[s] >> 32));
+                cand_alpha[o + s] = al[s];
+                cand_vel[o + s] = 0xFFFF - (int)(lo >> 16);
+                cand_nobs[o + s] = (int16_t)(lo & 0xFFFFu);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Final ordering: one thread per pixel ranks its candidates by counting the
+// candidates that precede each one, then writes the first k by rank.
+// ---------------------------------------------------------------------------
+template <int KM>
+__global__ __launch_bounds__(256) void topk_kernel(
+    int64_t npix, int k_cand, int k, const float *__restrict__ cand_nu,
+    const float *__restrict__ cand_alpha, const int32_t *__restrict__ cand_vel,
+    const int16_t *__restrict__ cand_nobs, float *__restrict__ nu, float *__restrict__ alpha,
+    int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const size_t ib = (size_t)p * (size_t)k_cand;
+    const size_t ob = (size_t)p * (size_t)k;
+    uint64_t key[KM];
+#pragma unroll
+    for (int s = 0; s < KM; ++s) {
+        key[s] = 0;
+        if (s < k_cand)
+            key[s] = make_key(cand_nu[ib + s], cand_vel[ib + s], (uint16_t)cand_nobs[ib + s]);
+    }
+    for (int s = 0; s < k_cand; ++s) {
+        const uint64_t ks = make_key(cand_nu[ib + s], cand_vel[ib + s],
+                                     (uint16_t)cand_nobs[ib + s]);
+        int rank = 0;
+#pragma unroll
+        for (int r = 0; r < KM; ++r) rank += key[r] > ks;
+        if (rank < k) {
+            nu[ob + rank] = cand_nu[ib + s];
+            alpha[ob + rank] = cand_alpha[ib + s];
+            vel[ob + rank] = cand_vel[ib + s];
+            nobs[ob + rank] = cand_nobs[ib + s];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers.
+// ---------------------------------------------------------------------------
+kb_status launch_status(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(KB_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+    return KB_OK;
+}
+
+template <int KM, int NB>
+kb_status launch_search_nb(const float2 *planes, int n_img, int h, int w, const int2 *disp,
+                           int n_vel, int k_cand, float *cn, float *ca, int32_t *cv,
+                           int16_t *co, hipStream_t stream) {
+    TileMap tm;
+    tm.nseg = (w + 63) / 64;
+    tm.h = h;
+    tm.strip = tm.nseg < 4 ? tm.nseg : 4;
+    tm.nblocks = tm.nseg * h;
+    hipLaunchKernelGGL((search_kernel<KM, NB>), dim3(tm.nblocks), dim3(64), 0, stream, planes,
+                       n_img, h, w, disp, n_vel, k_cand, tm, cn, ca, cv, co);
+    return launch_status("search_kernel");
+}
+
+template <int KM>
+kb_status launch_search_km(const float2 *planes, int n_img, int h, int w, const int2 *disp,
+                           int n_vel, int k_cand, float *cn, float *ca, int32_t *cv,
+                           int16_t *co, hipStream_t stream) {
+    if (n_img <= 8)
+        return launch_search_nb<KM, 8>(planes, n_img, h, w, disp, n_vel, k_cand, cn, ca, cv, co,
+                                       stream);
+    return launch_search_nb<KM, 16>(planes, n_img, h, w, disp, n_vel, k_cand, cn, ca, cv, co,
+                                    stream);
+}
+
+template <int KM>
+kb_status launch_topk_km(int64_t npix, int k_cand, int k, const float *cn, const float *ca,
+                         const int32_t *cv, const int16_t *co, float *nu, float *al,
+                         int32_t *vi, int16_t *no, hipStream_t stream) {
+    const int64_t blocks = (npix + 255) / 256;
+    hipLaunchKernelGGL((topk_kernel<KM>), dim3((unsigned)blocks), dim3(256), 0, stream, npix,
+                       k_cand, k, cn, ca, cv, co, nu, al, vi, no);
+    return launch_status("topk_kernel");
+}
+
+#define KB_DISPATCH_KM(kc, FN, ...)                  \
+    ((kc) <= 8    ? FN<8>(__VA_ARGS__)               \
+     : (kc) <= 16 ? FN<16>(__VA_ARGS__)              \
+     : (kc) <= 24 ? FN<24>(__VA_ARGS__)              \
+     : (kc) <= 32 ? FN<32>(__VA_ARGS__)              \
+     : (kc) <= 40 ? FN<40>(__VA_ARGS__)              \
+     : (kc) <= 48 ? FN<48>(__VA_ARGS__)              \
+     : (kc) <= 56 ? FN<56>(__VA_ARGS__)              \
+                  : FN<64>(__VA_ARGS__))
+
+kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
+    if (n_img < 1 || n_img > 32767)
+        return fail(KB_EINVAL, "n_img must be in [1, 32767] (got %lld)", (long long)n_img);
+    if (h < 1 || w < 1) return fail(KB_EINVAL, "h and w must be >= 1");
+    if (w > (int64_t(1) << 27)) return fail(KB_EINVAL, "w must be <= 2^27");
+    if (h > 2147483647LL) return fail(KB_EINVAL, "h must be < 2^31");
+    const int64_t nseg = (w + 63) / 64;
+    if (nseg * h > 2147483647LL) return fail(KB_EINVAL, "frame too large for one launch");
+    return KB_OK;
+}
+
+// Copy the clamped displacement table into the workspace.  The host copy is
+// pageable and temporary, so the call waits until it has reached the device.
+kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+                       int64_t h, int64_t w, void *workspace, hipStream_t stream) {
+    std::vector<int32_t> table(static_cast<size_t>(n_img) * n_vel * 2);
+    displacement_table(t, n_img, vel, n_vel, table.data(), w, h);
+    hipError_t e = hipMemcpyAsync(workspace, table.data(), table.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+        return fail(KB_EDEVICE, "displacement table upload failed: %s", hipGetErrorString(e));
+    return KB_OK;
+}
+
+}  // namespace
+}  // namespace kbmi
+
+using namespace kbmi;
+
+extern "C" {
+
+kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mask,
+                          int64_t n_img, int64_t h, int64_t w, const float *psf,
+                          int64_t psf_h, int64_t psf_w, float *psi_phi, int32_t lp_dtype,
+                          void *psi_phi_lp, float *lp_scale, void *stream) {
+    clear_error();
+    if (!img || !var || !psf || !psi_phi)
+        return fail(KB_EINVAL, "img, var, psf and psi_phi must be non-null");
+    kb_status st = check_frame(n_img, h, w);
+    if (st != KB_OK) return st;
+    if (psf_h < 1 || psf_w < 1 || psf_h % 2 == 0 || psf_w % 2 == 0)
+        return fail(KB_EINVAL, "PSF sizes must be odd and >= 1 (got %lld x %lld)",
+                    (long long)psf_h, (long long)psf_w);
+    if (psf_h > KB_MAX_PSF || psf_w > KB_MAX_PSF)
+        return fail(KB_EUNSUPPORTED, "PSF sides above %d are not supported", KB_MAX_PSF);
+    if (n_img > 65535 || (h + PP_TH - 1) / PP_TH > 65535)
+        return fail(KB_EUNSUPPORTED, "frame or stack too large for one plane launch");
+    if (lp_dtype != KB_F32) {
+        if (lp_dtype != KB_F16 && lp_dtype != KB_BF16)
+            return fail(KB_EINVAL, "lp_dtype must be KB_F32, KB_F16 or KB_BF16");
+        return fail(KB_EUNSUPPORTED, "16-bit plane copies are not implemented in this build");
+    }
+    (void)psi_phi_lp;
+    (void)lp_scale;
+    PsfTaps taps{};
+    for (int64_t u = 0; u < psf_h * psf_w; ++u) taps.t[u] = psf[u];
+    const dim3 grid((unsigned)((w + PP_TW - 1) / PP_TW), (unsigned)((h + PP_TH - 1) / PP_TH),
+                    (unsigned)n_img);
+    hipLaunchKernelGGL(psi_phi_kernel, grid, dim3(PP_THREADS), 0, (hipStream_t)stream, img, var,
+                       mask, (int)h, (int)w, (int)psf_h, (int)psf_w, taps,
+                       reinterpret_cast<float2 *>(psi_phi));
+    return launch_status("psi_phi_kernel");
+}
+
+kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, int64_t n_img,
+                    int64_t h, int64_t w, const double *t, const double *vel, int64_t n_vel,
+                    int64_t k_cand, float *cand_nu, float *cand_alpha, int32_t *cand_vel,
+                    int16_t *cand_nobs, void *workspace, size_t workspace_bytes,
+                    void *stream) {
+    clear_error();
+    if (!planes || !cand_nu || !cand_alpha || !cand_vel || !cand_nobs)
+        return fail(KB_EINVAL, "planes and candidate outputs must be non-null");
+    kb_status st = check_frame(n_img, h, w);
+    if (st != KB_OK) return st;
+    if (n_vel < 1 || n_vel > 65535)
+        return fail(KB_EINVAL, "n_vel must be in [1, 65535] (got %lld)", (long long)n_vel);
+    if (k_cand < 1 || k_cand > n_vel)
+        return fail(KB_EINVAL, "k_cand must be in [1, n_vel] (got %lld)", (long long)k_cand);
+    if (k_cand > KB_MAX_KCAND)
+        return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
+    st = check_times_velocities(t, n_img, vel, n_vel);
+    if (st != KB_OK) return st;
+    if (dtype != KB_F32) {
+        if (dtype != KB_F16 && dtype != KB_BF16)
+            return fail(KB_EINVAL, "dtype must be KB_F32, KB_F16 or KB_BF16");
+        return fail(KB_EUNSUPPORTED, "16-bit planes are not implemented in this build");
+    }
+    (void)lp_scale;
+    if (!workspace) return fail(KB_EINVAL, "workspace must be non-null");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(KB_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < table_bytes(n_img, n_vel))
+        return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)",
+                    table_bytes(n_img, n_vel), workspace_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    st = upload_table(t, n_img, vel, n_vel, h, w, workspace, s);
+    if (st != KB_OK) return st;
+    const int kc = (int)k_cand;
+    return KB_DISPATCH_KM(kc, launch_search_km, reinterpret_cast<const float2 *>(planes),
+                          (int)n_img, (int)h, (int)w, reinterpret_cast<const int2 *>(workspace),
+                          (int)n_vel, kc, cand_nu, cand_alpha, cand_vel, cand_nobs, s);
+}
+
+kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
+                  const double *t, const double *vel, int64_t n_vel, const float *cand_nu,
+                  const float *cand_alpha, const int32_t *cand_vel, const int16_t *cand_nobs,
+                  int64_t k_cand, int64_t k, float *nu, float *alpha, int32_t *vel_idx,
+                  int16_t *nobs, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!cand_nu || !cand_alpha || !cand_vel || !cand_nobs || !nu || !alpha || !vel_idx || !nobs)
+        return fail(KB_EINVAL, "candidate inputs and outputs must be non-null");
+    kb_status st = check_frame(n_img, h, w);
+    if (st != KB_OK) return st;
+    if (k_cand < 1 || k < 1 || k > k_cand)
+        return fail(KB_EINVAL, "need 1 <= k <= k_cand (got k=%lld, k_cand=%lld)", (long long)k,
+                    (long long)k_cand);
+    if (k_cand > KB_MAX_KCAND)
+        return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
+    if (psi_phi_f32 != nullptr)
+        return fail(KB_EUNSUPPORTED, "re-scoring is not implemented in this build");
+    (void)t;
+    (void)vel;
+    (void)n_vel;
+    (void)workspace;
+    (void)workspace_bytes;
+    const int64_t npix = h * w;
+    if ((npix + 255) / 256 > 2147483647LL) return fail(KB_EINVAL, "frame too large");
+    const int kc = (int)k_cand;
+    return KB_DISPATCH_KM(kc, launch_topk_km, npix, kc, (int)k, cand_nu, cand_alpha, cand_vel,
+                          cand_nobs, nu, alpha, vel_idx, nobs, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,196 @@
+"""ctypes binding of libkbmi.so: argument marshalling only.
+
+Every step of the search runs inside the HIP library.  This module turns
+torch device tensors into pointers, passes torch's current HIP stream, and
+raises KbError with the library's message for any non-OK status.  There is no
+fallback: if libkbmi.so is missing, loading fails with an ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkbmi.so")
+
+KB_OK, KB_EINVAL, KB_ENOMEM, KB_EDEVICE, KB_EUNSUPPORTED = 0, -1, -2, -3, -4
+KB_F32, KB_F16, KB_BF16 = 0, 1, 2
+_STATUS = {0: "KB_OK", -1: "KB_EINVAL", -2: "KB_ENOMEM", -3: "KB_EDEVICE", -4: "KB_EUNSUPPORTED"}
+
+_lock = threading.Lock()
+_lib = None
+
+_p, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+_SIGNATURES = {
+    "kb_abi_version": (ctypes.c_int, []),
+    "kb_last_error": (ctypes.c_char_p, []),
+    "kb_displacements": (ctypes.c_int, [_p, _i64, _p, _i64, _p]),
+    "kb_make_psi_phi": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _p, _i64, _i64, _p, _i32,
+                                       _p, _p, _p]),
+    "kb_search_workspace_bytes": (_sz, [_i64, _i64]),
+    "kb_search": (ctypes.c_int, [_p, _i32, _p, _i64, _i64, _i64, _p, _p, _i64, _i64, _p, _p, _p,
+                                 _p, _p, _sz, _p]),
+    "kb_topk": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64,
+                               _p, _p, _p, _p, _p, _sz, _p]),
+}
+
+
+class KbError(RuntimeError):
+    """A libkbmi call returned a non-OK status."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def load() -> ctypes.CDLL:
+    """Load libkbmi.so once; raises ImportError if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -m paper_1901_02492_amd.build`")
+            lib = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != KB_OK:
+        raise KbError(status, load().kb_last_error().decode())
+
+
+def _host_f64(a, shape_last=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape_last is not None:
+        a = a.reshape(-1, shape_last)
+    return a
+
+
+def displacements(t, vel) -> np.ndarray:
+    """Host table int32 [V][N][2] of the offsets every kernel uses."""
+    t = _host_f64(t)
+    vel = _host_f64(vel, 2)
+    out = np.empty((vel.shape[0], t.size, 2), dtype=np.int32)
+    _check(load().kb_displacements(t.ctypes.data, t.size, vel.ctypes.data, vel.shape[0],
+                                   out.ctypes.data))
+    return out
+
+
+def search_workspace_bytes(n_img: int, n_vel: int) -> int:
+    return int(load().kb_search_workspace_bytes(n_img, n_vel))
+
+
+# ---------------------------------------------------------------------------
+# Device calls (torch tensors on a HIP device).
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dev(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def make_psi_phi(img, var, mask, psf, out=None, stream=None):
+    """psi/phi planes float32 [N][H][W][2] from device img, var (float32) and
+    mask (uint8 or None); psf is a host float32 [ph][pw] array."""
+    torch = _torch()
+    n, h, w = img.shape
+    psf = np.ascontiguousarray(np.asarray(psf, dtype=np.float32))
+    if out is None:
+        out = torch.empty((n, h, w, 2), dtype=torch.float32, device=img.device)
+    mp = 0 if mask is None else _dev(mask, torch.uint8, "mask")
+    _check(load().kb_make_psi_phi(_dev(img, torch.float32, "img"),
+                                  _dev(var, torch.float32, "var"), mp or None, n, h, w,
+                                  psf.ctypes.data, psf.shape[0], psf.shape[1],
+                                  _dev(out, torch.float32, "psi_phi"), KB_F32, None, None,
+                                  _stream(stream)))
+    return out
+
+
+def alloc_candidates(h, w, k, device):
+    torch = _torch()
+    return (torch.empty((h, w, k), dtype=torch.float32, device=device),
+            torch.empty((h, w, k), dtype=torch.float32, device=device),
+            torch.empty((h, w, k), dtype=torch.int32, device=device),
+            torch.empty((h, w, k), dtype=torch.int16, device=device))
+
+
+def alloc_workspace(n_img, n_vel, device):
+    torch = _torch()
+    nb = search_workspace_bytes(n_img, n_vel)
+    return torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+
+
+def search(planes, t, vel, k_cand, out=None, workspace=None, stream=None):
+    """kb_search on float32 planes [N][H][W][2]; returns (nu, alpha, vel, nobs)
+    candidate tensors [H][W][k_cand]."""
+    torch = _torch()
+    n, h, w, two = planes.shape
+    assert two == 2
+    t = _host_f64(t)
+    vel = _host_f64(vel, 2)
+    if out is None:
+        out = alloc_candidates(h, w, k_cand, planes.device)
+    if workspace is None:
+        workspace = alloc_workspace(n, vel.shape[0], planes.device)
+    cn, ca, cv, co = out
+    _check(load().kb_search(_dev(planes, torch.float32, "planes"), KB_F32, None, n, h, w,
+                            t.ctypes.data, vel.ctypes.data, vel.shape[0], k_cand,
+                            _dev(cn, torch.float32, "cand_nu"),
+                            _dev(ca, torch.float32, "cand_alpha"),
+                            _dev(cv, torch.int32, "cand_vel"),
+                            _dev(co, torch.int16, "cand_nobs"),
+                            _dev(workspace, torch.uint8, "workspace"), workspace.numel(),
+                            _stream(stream)))
+    return out
+
+
+def topk(cand, k, n_img, out=None, stream=None):
+    """kb_topk without re-scoring: rank-ordered (nu, alpha, vel, nobs) [H][W][k]."""
+    torch = _torch()
+    cn, ca, cv, co = cand
+    h, w, kc = cn.shape
+    if out is None:
+        out = alloc_candidates(h, w, k, cn.device)
+    nu, al, vi, no = out
+    _check(load().kb_topk(None, n_img, h, w, None, None, 0,
+                          _dev(cn, torch.float32, "cand_nu"), _dev(ca, torch.float32, "cand_alpha"),
+                          _dev(cv, torch.int32, "cand_vel"), _dev(co, torch.int16, "cand_nobs"),
+                          kc, k, _dev(nu, torch.float32, "nu"), _dev(al, torch.float32, "alpha"),
+                          _dev(vi, torch.int32, "vel"), _dev(no, torch.int16, "nobs"), None, 0,
+                          _stream(stream)))
+    return out
+
+
+def run_search(img, var, mask, t, psf, vel, k, k_cand=None, stream=None):
+    """The whole path on device inputs: planes -> search -> top-k.
+    Returns (planes, (nu, alpha, vel, nobs))."""
+    k_cand = k if k_cand is None else k_cand
+    planes = make_psi_phi(img, var, mask, psf, stream=stream)
+    cand = search(planes, t, vel, k_cand, stream=stream)
+    res = topk(cand, k, img.shape[0], stream=stream)
+    return planes, res

@@ -1,0 +1,133 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and exports
+every symbol the header declares, the displacement table equals the oracle's
+bit for bit, and invalid arguments are rejected before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_02492_amd import lib, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "kbmi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(kb_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _header_functions()
+    assert {"kb_make_psi_phi", "kb_search", "kb_topk", "kb_displacements"} <= set(names)
+    L = lib.load()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_abi_version():
+    assert lib.load().kb_abi_version() == 1
+
+
+@pytest.mark.parametrize("which", ["small", "survey", "random"])
+def test_displacements_equal_oracle_bit_for_bit(which):
+    if which == "small":
+        s = synth.small_stack()
+        t, vel = s.t, s.vel
+    elif which == "survey":
+        t = np.array([n + 0.06 * e for n in range(3) for e in range(5)])
+        vel = synth.velocity_grid_polar(np.linspace(80, 400, 25), np.linspace(-0.5, 0.5, 24))
+    else:
+        rng = np.random.default_rng(4)
+        t = np.sort(rng.uniform(0, 3, 40))
+        vel = rng.uniform(-500, 500, (3000, 2))
+        vel[:100] = np.round(vel[:100]) + 0.5
+    got = lib.displacements(t, vel)
+    ref = oracle.displacements(t, vel)
+    assert got.dtype == np.int32
+    assert np.array_equal(got.astype(np.int64), ref)
+
+
+def test_displacement_half_ties_in_library():
+    t = np.array([0.0, 0.05, 0.15])
+    vel = np.array([[-50.0, -30.0], [-10.0, 30.0]])
+    d = lib.displacements(t, vel)
+    assert d[0, 1].tolist() == [-2, -1] and d[0, 2].tolist() == [-7, -4]
+    assert d[1, 1].tolist() == [0, 2] and d[1, 2].tolist() == [-1, 5]
+
+
+@pytest.mark.parametrize("t,vel,msg", [
+    ([0.0, 1.0, 0.5], [[1.0, 1.0]], "non-decreasing"),
+    ([0.0, np.nan], [[1.0, 1.0]], "not finite"),
+    ([0.0, 1.0], [[np.inf, 1.0]], "not finite"),
+    ([0.0, 2.0], [[6e8, 0.0]], "2^30"),
+])
+def test_displacements_reject_bad_inputs(t, vel, msg):
+    with pytest.raises(lib.KbError) as e:
+        lib.displacements(t, vel)
+    assert e.value.status == lib.KB_EINVAL and msg in str(e.value)
+
+
+def _search_call(**over):
+    """Call kb_search with fake device pointers; only argument checks may run."""
+    fake = 1 << 20
+    a = dict(planes=fake, dtype=0, scale=None, n=3, h=8, w=8, t=np.array([0.0, 1.0, 2.0]),
+             vel=np.zeros((4, 2)), nv=4, kc=2, ws=fake, wsb=1 << 20)
+    a.update(over)
+    t = np.ascontiguousarray(a["t"], dtype=np.float64)
+    vel = np.ascontiguousarray(a["vel"], dtype=np.float64)
+    L = lib.load()
+    st = L.kb_search(a["planes"], a["dtype"], a["scale"], a["n"], a["h"], a["w"], t.ctypes.data,
+                     vel.ctypes.data, a["nv"], a["kc"], fake, fake, fake, fake, a["ws"], a["wsb"],
+                     None)
+    return st, L.kb_last_error().decode()
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(planes=None), lib.KB_EINVAL),
+    (dict(n=0), lib.KB_EINVAL),
+    (dict(h=0), lib.KB_EINVAL),
+    (dict(kc=0), lib.KB_EINVAL),
+    (dict(kc=5), lib.KB_EINVAL),                       # k_cand > n_vel
+    (dict(kc=65, nv=100, vel=np.zeros((100, 2))), lib.KB_EUNSUPPORTED),
+    (dict(t=np.array([0.0, 2.0, 1.0])), lib.KB_EINVAL),
+    (dict(dtype=7), lib.KB_EINVAL),
+    (dict(dtype=1), lib.KB_EUNSUPPORTED),
+    (dict(ws=None), lib.KB_EINVAL),
+    (dict(ws=(1 << 20) + 4), lib.KB_EINVAL),            # misaligned workspace
+    (dict(wsb=16), lib.KB_ENOMEM),
+    (dict(w=(1 << 27) + 1), lib.KB_EINVAL),
+])
+def test_search_rejects_bad_arguments_before_enqueue(over, status):
+    st, msg = _search_call(**over)
+    assert st == status and msg
+
+
+def test_make_psi_phi_rejects_bad_psf():
+    L = lib.load()
+    psf = np.ones((4, 5), np.float32)
+    fake = 1 << 20
+    st = L.kb_make_psi_phi(fake, fake, None, 2, 8, 8, psf.ctypes.data, 4, 5, fake, 0, None,
+                           None, None)
+    assert st == lib.KB_EINVAL and "odd" in L.kb_last_error().decode()
+    big = np.ones((27, 27), np.float32)
+    st = L.kb_make_psi_phi(fake, fake, None, 2, 8, 8, big.ctypes.data, 27, 27, fake, 0, None,
+                           None, None)
+    assert st == lib.KB_EUNSUPPORTED
+
+
+def test_topk_rejects_k_above_k_cand():
+    L = lib.load()
+    fake = 1 << 20
+    st = L.kb_topk(None, 3, 8, 8, None, None, 0, fake, fake, fake, fake, 4, 5, fake, fake, fake,
+                   fake, None, 0, None)
+    assert st == lib.KB_EINVAL
+
+
+def test_workspace_size():
+    assert lib.search_workspace_bytes(15, 600) >= 15 * 600 * 8
+    assert lib.search_workspace_bytes(15, 600) % 256 == 0
+    assert lib.search_workspace_bytes(0, 600) == 0
