@@ -38,22 +38,24 @@ def _run(cmd, verbose):
         print(r.stderr, file=sys.stderr)
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile every source and link libkbmi.so next to this file; returns its path."""
+def build_library(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source and link libkbmi.so (next to this file unless `out`
+    is given); `defines` are extra -D options.  Returns the library path."""
+    dflags = [f"-D{d}" for d in defines]
     with tempfile.TemporaryDirectory(prefix="kbmi_build_") as tmp:
         objs = []
         host_obj = os.path.join(tmp, "kbmi_host.o")
-        _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "kbmi_host.cpp"), "-o", host_obj],
+        _run(["g++", *HOST_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_host.cpp"), "-o", host_obj],
              verbose)
         objs.append(host_obj)
         dev_obj = os.path.join(tmp, "kbmi_kernels.o")
-        _run([HIPCC, *DEVICE_FLAGS, "-c", os.path.join(CSRC, "kbmi_kernels.hip"), "-o", dev_obj],
+        _run([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_kernels.hip"), "-o", dev_obj],
              verbose)
         objs.append(dev_obj)
-        tmp_lib = LIB + ".tmp"
+        tmp_lib = out + ".tmp"
         _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp_lib, *objs], verbose)
-        os.replace(tmp_lib, LIB)
-    return LIB
+        os.replace(tmp_lib, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -3,10 +3,13 @@
 // image).  Built with -ffp-contract=off: the product v * tau, the sum with 0.5
 // and the floor must stay three separately rounded IEEE double operations so
 // that every offset equals the documented definition bit for bit.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "kbmi_internal.h"
 
@@ -72,6 +75,61 @@ void displacement_table(const double *t, int64_t n_img, const double *vel, int64
     }
 }
 
+// Index along a Hilbert curve of order 16 (rotate-and-flip construction).
+static uint32_t hilbert_index(uint32_t x, uint32_t y) {
+    uint32_t d = 0;
+    for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u;
+        const uint32_t ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = (s - 1) - (x & (s - 1)) + (x & ~(s - 1));
+                y = (s - 1) - (y & (s - 1)) + (y & ~(s - 1));
+            }
+            const uint32_t tmp = x;
+            x = y;
+            y = tmp;
+        }
+    }
+    return d;
+}
+
+#ifndef KBMI_HILBERT_ORDER
+#define KBMI_HILBERT_ORDER 1
+#endif
+
+void velocity_order(const double *vel, int64_t n_vel, int32_t *order) {
+    if (!KBMI_HILBERT_ORDER) {
+        for (int64_t j = 0; j < n_vel; ++j) order[j] = static_cast<int32_t>(j);
+        return;
+    }
+    double lo[2] = {vel[0], vel[1]}, hi[2] = {vel[0], vel[1]};
+    for (int64_t j = 1; j < n_vel; ++j)
+        for (int a = 0; a < 2; ++a) {
+            lo[a] = std::min(lo[a], vel[2 * j + a]);
+            hi[a] = std::max(hi[a], vel[2 * j + a]);
+        }
+    std::vector<std::pair<uint32_t, int32_t>> keyed(static_cast<size_t>(n_vel));
+    for (int64_t j = 0; j < n_vel; ++j) {
+        uint32_t q[2];
+        for (int a = 0; a < 2; ++a) {
+            const double span = hi[a] - lo[a];
+            const double u = span > 0 ? (vel[2 * j + a] - lo[a]) / span : 0.0;
+            q[a] = static_cast<uint32_t>(std::min(65535.0, std::max(0.0, u * 65535.0)));
+        }
+        keyed[static_cast<size_t>(j)] = {hilbert_index(q[0], q[1]), static_cast<int32_t>(j)};
+    }
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (int64_t j = 0; j < n_vel; ++j) order[j] = keyed[static_cast<size_t>(j)].second;
+}
+
+size_t order_bytes(int64_t n_vel) {
+    const size_t raw = static_cast<size_t>(n_vel) * sizeof(int32_t);
+    return (raw + 255) & ~static_cast<size_t>(255);
+}
+
 size_t table_bytes(int64_t n_img, int64_t n_vel) {
     const size_t raw = static_cast<size_t>(n_img) * static_cast<size_t>(n_vel) * 2 * sizeof(int32_t);
     return (raw + 255) & ~static_cast<size_t>(255);
@@ -97,7 +155,7 @@ kb_status kb_displacements(const double *t, int64_t n_img, const double *vel, in
 
 size_t kb_search_workspace_bytes(int64_t n_img, int64_t n_vel) {
     if (n_img < 1 || n_vel < 1) return 0;
-    return kbmi::table_bytes(n_img, n_vel);
+    return kbmi::table_bytes(n_img, n_vel) + kbmi::order_bytes(n_vel);
 }
 
 }  // extern "C"

@@ -25,7 +25,16 @@ kb_status check_times_velocities(const double *t, int64_t n_img, const double *v
 void displacement_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                         int32_t *disp, int64_t clamp_w, int64_t clamp_h);
 
-// Device workspace layout: the clamped displacement table at offset 0.
+// Order in which the search visits the velocities: along a Hilbert curve over
+// the (vx, vy) bounding box, so consecutive velocities shift every image's
+// gather window by little and neighbouring workgroups reuse cached rows.  Any
+// order gives the same result (ranking uses the original index).
+void velocity_order(const double *vel, int64_t n_vel, int32_t *order);
+
+// Device workspace layout: the clamped displacement table [n_vel][n_img][2]
+// in visiting order at offset 0, then the original index of each visited
+// velocity (int32 [n_vel]) at table_bytes().
 size_t table_bytes(int64_t n_img, int64_t n_vel);
+size_t order_bytes(int64_t n_vel);
 
 }  // namespace kbmi

@@ -22,6 +22,14 @@
 
 #include "kbmi_internal.h"
 
+// Launch-shape defaults (compile-time tunables).
+#ifndef KBMI_STRIP_TILES
+#define KBMI_STRIP_TILES 4      // start-pixel tiles per strip of the tile order
+#endif
+#ifndef KBMI_QUEUE
+#define KBMI_QUEUE 16           // queued candidates per lane before a merge
+#endif
+
 namespace kbmi {
 namespace {
 
@@ -139,17 +147,6 @@ __device__ inline uint64_t make_key(float nu, int j, uint32_t nobs) {
            (uint64_t)(((uint32_t)(0xFFFF - j) << 16) | (nobs & 0xFFFFu));
 }
 
-// Scores of one trajectory (Sec. 2.1.5: alpha_ML = Psi / Phi, nu = Psi / sqrt(Phi)).
-__device__ inline void score(float P, float F, float &nu, float &alpha) {
-    if (F > 0.f) {
-        nu = P / sqrtf(F);
-        alpha = P / F;
-    } else {
-        nu = -INFINITY;
-        alpha = 0.f;
-    }
-}
-
 // Start-pixel tiles: one wave = 64 adjacent pixels of one row.  Tiles are
 // enumerated in strips `strip` tiles wide (all rows of a strip, then the next
 // strip) so that consecutive workgroups cover a compact 2-D patch, and the
@@ -183,18 +180,42 @@ struct TileMap {
 };
 
 // ---------------------------------------------------------------------------
-// Trajectory search.  KM = register list length (>= k_cand), NB = images whose
-// loads are issued together before they are summed in image order.
+// Trajectory search.
+//
+// One wave (one workgroup) owns 64 adjacent start pixels of one row and walks
+// every velocity in the host-chosen visiting order.  Per velocity each lane
+// gathers its trajectory's N (psi, phi) pairs (one coalesced 512-byte run per
+// image across the wave), sums them in image order and scores nu.
+//
+// Per-pixel selection keeps a descending list of KM >= k_cand keys in
+// registers.  Inserting into it costs a compare-and-swap per slot, and the wave
+// pays for it whenever any lane inserts, so candidates are first filtered
+// against a per-lane threshold (the list's last key at the last merge) and
+// parked in a per-lane LDS queue of PB entries; the queue is merged into the
+// list only when some lane's queue is full (and at the end).  A candidate that
+// fails the threshold can never enter the final list: the threshold only rises.
+//
+// The loads of up to NB images are issued together before they are summed in
+// image order; larger stacks are summed in batches of NB images.  The kernel
+// is bounded to two waves per SIMD: memory-level parallelism comes from the
+// waves, each holding one velocity's NB loads in flight.
 // ---------------------------------------------------------------------------
-template <int KM, int NB>
-__global__ __launch_bounds__(64) void search_kernel(
+template <int KM, int NB, int PB>
+__global__ __launch_bounds__(64, 2) void search_kernel(
     const float2 *__restrict__ planes, int n_img, int h, int w,
-    const int2 *__restrict__ disp, int n_vel, int k_cand, TileMap tiles,
-    float *__restrict__ cand_nu, float *__restrict__ cand_alpha,
+    const int2 *__restrict__ disp, const int32_t *__restrict__ vel_index, int n_vel,
+    int k_cand, TileMap tiles, float *__restrict__ cand_nu, float *__restrict__ cand_alpha,
     int32_t *__restrict__ cand_vel, int16_t *__restrict__ cand_nobs) {
+    constexpr int kLdsWords = (3 * PB > KM ? 3 * PB : KM) * 64;
+    __shared__ uint32_t lds[kLdsWords];
+    uint32_t *q_hi = lds;
+    uint32_t *q_lo = lds + PB * 64;
+    float *q_al = reinterpret_cast<float *>(lds + 2 * PB * 64);
+
+    const int lane = (int)threadIdx.x;
     int row, seg;
     tiles.map(blockIdx.x, row, seg);
-    const int x0 = seg * 64 + (int)threadIdx.x;
+    const int x0 = seg * 64 + lane;
     const uint32_t row_bytes = (uint32_t)w * 8u;
     const size_t img_stride = (size_t)h * (size_t)w;
 
@@ -205,100 +226,206 @@ __global__ __launch_bounds__(64) void search_kernel(
         key[s] = 0;
         al[s] = 0.f;
     }
+    uint64_t thr = 0;   // admission threshold (list tail at the last merge)
+    int nq = 0;         // queued candidates of this lane
 
-    for (int j = 0; j < n_vel; ++j) {
-        const int2 *dj = disp + (size_t)j * n_img;
-        float P = 0.f, F = 0.f;
-        uint32_t cnt = 0;
-        for (int i0 = 0; i0 < n_img; i0 += NB) {
-            u32x2 v[NB];
+    // Issue the loads of images [i0, i0 + NB) of visited velocity jj.  Slots
+    // past the last image, and rows outside the frame, get a zero-length
+    // buffer: their loads return 0 and add nothing, with no branch.
+    auto issue = [&](int jj, int i0, u32x2(&v)[NB]) {
+        const int2 *dj = disp + (size_t)jj * n_img;
+        // Recomputed per velocity (not hoisted): keeps 2 * NB image bases out
+        // of the scalar register file.
+        const char *pbase = reinterpret_cast<const char *>(planes);
+        asm volatile("" : "+s"(pbase));
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int i = i0 + b;
-                if (i < n_img) {
-                    const int2 d = dj[i];
-                    const int yy = row + d.y;
-                    const bool in_rows = (unsigned)yy < (unsigned)h;
-                    const float2 *base = planes + (size_t)i * img_stride +
-                                         (size_t)(in_rows ? yy : 0) * (size_t)w;
-                    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base, in_rows ? row_bytes : 0u);
-                    v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + d.x) * 8, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if (i0 + b < n_img) {
-                    P += __uint_as_float(v[b].x);
-                    F += __uint_as_float(v[b].y);
-                    cnt += v[b].y != 0u;
-                }
-            }
+        for (int b = 0; b < NB; ++b) {
+            const int i = i0 + b;
+            const bool have = i < n_img;
+            const int2 d = dj[have ? i : 0];
+            const int yy = row + d.y;
+            const bool in_rows = have && (unsigned)yy < (unsigned)h;
+            const size_t off = ((size_t)(have ? i : 0) * img_stride +
+                                (size_t)(in_rows ? yy : 0) * (size_t)w) * sizeof(float2);
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(pbase + off, in_rows ? row_bytes : 0u);
+            v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + d.x) * 8, 0, 0);
         }
-        float nu, a;
-        score(P, F, nu, a);
-        uint64_t nk = make_key(nu, j, cnt);
-        if (nk > key[KM - 1]) {
-            // Insert into the descending list; the old last entry drops out.
+    };
+    // Sum in image order.  Empty slots hold +0, which leaves every sum unchanged.
+    auto accumulate = [&](const u32x2(&v)[NB], float &P, float &F) {
 #pragma unroll
-            for (int s = 0; s < KM; ++s) {
-                const bool c = nk > key[s];
-                const uint64_t tk = c ? key[s] : nk;
-                key[s] = c ? nk : key[s];
-                nk = tk;
-                const float ta = c ? al[s] : a;
-                al[s] = c ? a : al[s];
-                a = ta;
-            }
+        for (int b = 0; b < NB; ++b) {
+            P += __uint_as_float(v[b].x);
+            F += __uint_as_float(v[b].y);
         }
-    }
-
-    if (x0 < w) {
-        const size_t o = ((size_t)row * (size_t)w + (size_t)x0) * (size_t)k_cand;
+    };
+    // n_obs: stored phi is nonzero exactly at valid pixels; empty slots are 0.
+    auto count = [&](const u32x2(&v)[NB]) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) c += v[b].y != 0u;
+        return c;
+    };
+    auto insert = [&](uint64_t nk, float a) {
 #pragma unroll
         for (int s = 0; s < KM; ++s) {
-            if (s < k_cand) {
-                const uint32_t lo = (uint32_t)key[s];
-                cand_nu[o + s] = nu_from_order_bits((uint32_t)(key[s] >> 32));
-                cand_alpha[o + s] = al[s];
-                cand_vel[o + s] = 0xFFFF - (int)(lo >> 16);
-                cand_nobs[o + s] = (int16_t)(lo & 0xFFFFu);
+            const bool c = nk > key[s];
+            const uint64_t tk = c ? key[s] : nk;
+            key[s] = c ? nk : key[s];
+            nk = tk;
+            const float ta = c ? al[s] : a;
+            al[s] = c ? a : al[s];
+            a = ta;
+        }
+    };
+    auto merge_queue = [&]() {
+        for (int b = 0; b < PB; ++b) {
+            if (!__any(b < nq)) break;
+            if (b < nq) {
+                const uint64_t nk = ((uint64_t)q_hi[b * 64 + lane] << 32) | q_lo[b * 64 + lane];
+                if (nk > key[KM - 1]) insert(nk, q_al[b * 64 + lane]);
             }
         }
+        nq = 0;
+        thr = key[KM - 1];
+    };
+    // Score one trajectory (Sec. 2.1.5: nu = Psi / sqrt(Phi), alpha = Psi / Phi)
+    // and queue it if it beats the admission threshold.  n_obs only sits in
+    // the low bits of the key and never decides an order, so it is counted
+    // only for queued candidates.
+    auto finish = [&](int jj, float P, float F, uint32_t c) {
+        const float nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
+        const uint64_t nk = make_key(nu, vel_index[jj], 0u);
+        if (nk > thr) {
+            q_hi[nq * 64 + lane] = (uint32_t)(nk >> 32);
+            q_lo[nq * 64 + lane] = (uint32_t)nk | c;
+            q_al[nq * 64 + lane] = F > 0.f ? P / F : 0.f;
+            ++nq;
+        }
+        if (__any(nq == PB)) merge_queue();
+    };
+
+    if (n_img <= NB) {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            u32x2 v[NB];
+            issue(jj, 0, v);
+            float P = 0.f, F = 0.f;
+            accumulate(v, P, F);
+            finish(jj, P, F, count(v));
+        }
+    } else {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            float P = 0.f, F = 0.f;
+            uint32_t c = 0;
+            for (int i0 = 0; i0 < n_img; i0 += NB) {
+                u32x2 v[NB];
+                issue(jj, i0, v);
+                accumulate(v, P, F);
+                c += count(v);
+            }
+            finish(jj, P, F, c);
+        }
+    }
+    merge_queue();
+
+    // Write the rank-ordered list: stage each field through LDS so that the
+    // wave's stores cover the contiguous [pixels][k_cand] run of its pixels
+    // (one pixel's k_cand <= 64 entries per store instruction).
+    const int npx = (w - seg * 64) < 64 ? (w - seg * 64) : 64;
+    const size_t base = ((size_t)row * (size_t)w + (size_t)seg * 64) * (size_t)k_cand;
+    __syncthreads();
+#pragma unroll
+    for (int field = 0; field < 4; ++field) {
+#pragma unroll
+        for (int s = 0; s < KM; ++s) {
+            const uint32_t hi = (uint32_t)(key[s] >> 32), lo = (uint32_t)key[s];
+            uint32_t v;
+            if (field == 0) v = __float_as_uint(nu_from_order_bits(hi));
+            else if (field == 1) v = __float_as_uint(al[s]);
+            else if (field == 2) v = (uint32_t)(0xFFFF - (int)(lo >> 16));
+            else v = lo & 0xFFFFu;
+            lds[lane * KM + s] = v;
+        }
+        __syncthreads();
+        if (lane < k_cand) {
+            for (int p = 0; p < npx; ++p) {
+                const uint32_t v = lds[p * KM + lane];
+                const size_t o = base + (size_t)p * (size_t)k_cand + (size_t)lane;
+                if (field == 0) cand_nu[o] = __uint_as_float(v);
+                else if (field == 1) cand_alpha[o] = __uint_as_float(v);
+                else if (field == 2) cand_vel[o] = (int32_t)v;
+                else cand_nobs[o] = (int16_t)v;
+            }
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Final ordering: one thread per pixel ranks its candidates by counting the
-// candidates that precede each one, then writes the first k by rank.
+// Final selection.  One wave handles 64 consecutive pixels: their candidate
+// runs are loaded with coalesced reads into LDS, each lane checks that its
+// pixel's candidates are in rank order (kb_search leaves them so), and the
+// first k of every pixel are written back with coalesced stores.  A pixel
+// whose candidates are not in order is ranked by counting, for each
+// candidate, the candidates that precede it.
 // ---------------------------------------------------------------------------
 template <int KM>
-__global__ __launch_bounds__(256) void topk_kernel(
+__global__ __launch_bounds__(64) void topk_kernel(
     int64_t npix, int k_cand, int k, const float *__restrict__ cand_nu,
     const float *__restrict__ cand_alpha, const int32_t *__restrict__ cand_vel,
     const int16_t *__restrict__ cand_nobs, float *__restrict__ nu, float *__restrict__ alpha,
     int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
-    const size_t ib = (size_t)p * (size_t)k_cand;
-    const size_t ob = (size_t)p * (size_t)k;
-    uint64_t key[KM];
-#pragma unroll
-    for (int s = 0; s < KM; ++s) {
-        key[s] = 0;
-        if (s < k_cand)
-            key[s] = make_key(cand_nu[ib + s], cand_vel[ib + s], (uint16_t)cand_nobs[ib + s]);
+    __shared__ uint32_t s_nu[64 * KM], s_al[64 * KM], s_vel[64 * KM];
+    __shared__ uint16_t s_no[64 * KM];
+    __shared__ uint8_t s_rank[64 * KM];
+    const int lane = (int)threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int npx = (npix - p0) < 64 ? (int)(npix - p0) : 64;
+    const int total = npx * k_cand;
+    const size_t ib = (size_t)p0 * (size_t)k_cand;
+    for (int idx = lane; idx < total; idx += 64) {
+        s_nu[idx] = __float_as_uint(cand_nu[ib + idx]);
+        s_al[idx] = __float_as_uint(cand_alpha[ib + idx]);
+        s_vel[idx] = (uint32_t)cand_vel[ib + idx];
+        s_no[idx] = (uint16_t)cand_nobs[ib + idx];
     }
-    for (int s = 0; s < k_cand; ++s) {
-        const uint64_t ks = make_key(cand_nu[ib + s], cand_vel[ib + s],
-                                     (uint16_t)cand_nobs[ib + s]);
-        int rank = 0;
-#pragma unroll
-        for (int r = 0; r < KM; ++r) rank += key[r] > ks;
-        if (rank < k) {
-            nu[ob + rank] = cand_nu[ib + s];
-            alpha[ob + rank] = cand_alpha[ib + s];
-            vel[ob + rank] = cand_vel[ib + s];
-            nobs[ob + rank] = cand_nobs[ib + s];
+    __syncthreads();
+    auto key_at = [&](int idx) {
+        return make_key(__uint_as_float(s_nu[idx]), (int)s_vel[idx], s_no[idx]);
+    };
+    bool ordered = true;
+    if (lane < npx) {
+        const int o = lane * k_cand;
+        uint64_t prev = key_at(o);
+        for (int s = 1; s < k_cand; ++s) {
+            const uint64_t cur = key_at(o + s);
+            ordered = ordered && prev > cur;
+            prev = cur;
+        }
+    }
+    if (__all(ordered)) {
+        for (int idx = lane; idx < total; idx += 64) s_rank[idx] = (uint8_t)(idx % k_cand);
+    } else if (lane < npx) {
+        const int o = lane * k_cand;
+        for (int s = 0; s < k_cand; ++s) {
+            const uint64_t ks = key_at(o + s);
+            int r = 0;
+            for (int t = 0; t < k_cand; ++t) r += key_at(o + t) > ks;
+            s_rank[o + s] = (uint8_t)r;
+        }
+    }
+    __syncthreads();
+    // Scatter into the output by rank; entries ranked >= k are dropped.  The
+    // writes of a wave cover the contiguous [npx][k] run.
+    const size_t ob = (size_t)p0 * (size_t)k;
+    for (int idx = lane; idx < total; idx += 64) {
+        const int r = s_rank[idx];
+        if (r < k) {
+            const size_t o = ob + (size_t)(idx / k_cand) * (size_t)k + (size_t)r;
+            nu[o] = __uint_as_float(s_nu[idx]);
+            alpha[o] = __uint_as_float(s_al[idx]);
+            vel[o] = (int32_t)s_vel[idx];
+            nobs[o] = (int16_t)s_no[idx];
         }
     }
 }
@@ -315,35 +442,36 @@ kb_status launch_status(const char *what) {
 
 template <int KM, int NB>
 kb_status launch_search_nb(const float2 *planes, int n_img, int h, int w, const int2 *disp,
-                           int n_vel, int k_cand, float *cn, float *ca, int32_t *cv,
-                           int16_t *co, hipStream_t stream) {
+                           const int32_t *vel_index, int n_vel, int k_cand, float *cn, float *ca,
+                           int32_t *cv, int16_t *co, hipStream_t stream) {
+    constexpr int PB = KBMI_QUEUE;
     TileMap tm;
     tm.nseg = (w + 63) / 64;
     tm.h = h;
-    tm.strip = tm.nseg < 4 ? tm.nseg : 4;
+    tm.strip = tm.nseg < KBMI_STRIP_TILES ? tm.nseg : KBMI_STRIP_TILES;
     tm.nblocks = tm.nseg * h;
-    hipLaunchKernelGGL((search_kernel<KM, NB>), dim3(tm.nblocks), dim3(64), 0, stream, planes,
-                       n_img, h, w, disp, n_vel, k_cand, tm, cn, ca, cv, co);
+    hipLaunchKernelGGL((search_kernel<KM, NB, PB>), dim3(tm.nblocks), dim3(64), 0, stream,
+                       planes, n_img, h, w, disp, vel_index, n_vel, k_cand, tm, cn, ca, cv, co);
     return launch_status("search_kernel");
 }
 
 template <int KM>
 kb_status launch_search_km(const float2 *planes, int n_img, int h, int w, const int2 *disp,
-                           int n_vel, int k_cand, float *cn, float *ca, int32_t *cv,
-                           int16_t *co, hipStream_t stream) {
+                           const int32_t *vel_index, int n_vel, int k_cand, float *cn, float *ca,
+                           int32_t *cv, int16_t *co, hipStream_t stream) {
     if (n_img <= 8)
-        return launch_search_nb<KM, 8>(planes, n_img, h, w, disp, n_vel, k_cand, cn, ca, cv, co,
-                                       stream);
-    return launch_search_nb<KM, 16>(planes, n_img, h, w, disp, n_vel, k_cand, cn, ca, cv, co,
-                                    stream);
+        return launch_search_nb<KM, 8>(planes, n_img, h, w, disp, vel_index, n_vel, k_cand, cn,
+                                       ca, cv, co, stream);
+    return launch_search_nb<KM, 16>(planes, n_img, h, w, disp, vel_index, n_vel, k_cand, cn, ca,
+                                    cv, co, stream);
 }
 
 template <int KM>
 kb_status launch_topk_km(int64_t npix, int k_cand, int k, const float *cn, const float *ca,
                          const int32_t *cv, const int16_t *co, float *nu, float *al,
                          int32_t *vi, int16_t *no, hipStream_t stream) {
-    const int64_t blocks = (npix + 255) / 256;
-    hipLaunchKernelGGL((topk_kernel<KM>), dim3((unsigned)blocks), dim3(256), 0, stream, npix,
+    const int64_t blocks = (npix + 63) / 64;
+    hipLaunchKernelGGL((topk_kernel<KM>), dim3((unsigned)blocks), dim3(64), 0, stream, npix,
                        k_cand, k, cn, ca, cv, co, nu, al, vi, no);
     return launch_status("topk_kernel");
 }
@@ -373,10 +501,22 @@ kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
 // pageable and temporary, so the call waits until it has reached the device.
 kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                        int64_t h, int64_t w, void *workspace, hipStream_t stream) {
+    // Velocities in visiting order, then the table of the reordered grid.
+    std::vector<int32_t> order(static_cast<size_t>(n_vel));
+    velocity_order(vel, n_vel, order.data());
+    std::vector<double> vel_visit(static_cast<size_t>(n_vel) * 2);
+    for (int64_t j = 0; j < n_vel; ++j) {
+        vel_visit[2 * j] = vel[2 * order[j]];
+        vel_visit[2 * j + 1] = vel[2 * order[j] + 1];
+    }
     std::vector<int32_t> table(static_cast<size_t>(n_img) * n_vel * 2);
-    displacement_table(t, n_img, vel, n_vel, table.data(), w, h);
-    hipError_t e = hipMemcpyAsync(workspace, table.data(), table.size() * sizeof(int32_t),
+    displacement_table(t, n_img, vel_visit.data(), n_vel, table.data(), w, h);
+    char *ws = static_cast<char *>(workspace);
+    hipError_t e = hipMemcpyAsync(ws, table.data(), table.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + table_bytes(n_img, n_vel), order.data(),
+                           order.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess)
         return fail(KB_EDEVICE, "displacement table upload failed: %s", hipGetErrorString(e));
@@ -450,16 +590,18 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     if (!workspace) return fail(KB_EINVAL, "workspace must be non-null");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KB_EINVAL, "workspace must be 256-byte aligned");
-    if (workspace_bytes < table_bytes(n_img, n_vel))
-        return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)",
-                    table_bytes(n_img, n_vel), workspace_bytes);
+    const size_t ws_need = table_bytes(n_img, n_vel) + order_bytes(n_vel);
+    if (workspace_bytes < ws_need)
+        return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need, workspace_bytes);
     hipStream_t s = (hipStream_t)stream;
     st = upload_table(t, n_img, vel, n_vel, h, w, workspace, s);
     if (st != KB_OK) return st;
     const int kc = (int)k_cand;
+    const int32_t *vel_index = reinterpret_cast<const int32_t *>(
+        static_cast<const char *>(workspace) + table_bytes(n_img, n_vel));
     return KB_DISPATCH_KM(kc, launch_search_km, reinterpret_cast<const float2 *>(planes),
                           (int)n_img, (int)h, (int)w, reinterpret_cast<const int2 *>(workspace),
-                          (int)n_vel, kc, cand_nu, cand_alpha, cand_vel, cand_nobs, s);
+                          vel_index, (int)n_vel, kc, cand_nu, cand_alpha, cand_vel, cand_nobs, s);
 }
 
 kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
@@ -485,7 +627,7 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
     (void)workspace;
     (void)workspace_bytes;
     const int64_t npix = h * w;
-    if ((npix + 255) / 256 > 2147483647LL) return fail(KB_EINVAL, "frame too large");
+    if ((npix + 63) / 64 > 2147483647LL) return fail(KB_EINVAL, "frame too large");
     const int kc = (int)k_cand;
     return KB_DISPATCH_KM(kc, launch_topk_km, npix, kc, (int)k, cand_nu, cand_alpha, cand_vel,
                           cand_nobs, nu, alpha, vel_idx, nobs, (hipStream_t)stream);
