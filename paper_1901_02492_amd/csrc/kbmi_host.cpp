@@ -130,8 +130,11 @@ size_t order_bytes(int64_t n_vel) {
     return (raw + 255) & ~static_cast<size_t>(255);
 }
 
+int64_t table_stride(int64_t n_img) { return n_img <= 8 ? 8 : (n_img + 15) / 16 * 16; }
+
 size_t table_bytes(int64_t n_img, int64_t n_vel) {
-    const size_t raw = static_cast<size_t>(n_img) * static_cast<size_t>(n_vel) * 2 * sizeof(int32_t);
+    const size_t raw = static_cast<size_t>(table_stride(n_img)) * static_cast<size_t>(n_vel) * 2 *
+                       sizeof(int32_t);
     return (raw + 255) & ~static_cast<size_t>(255);
 }
 

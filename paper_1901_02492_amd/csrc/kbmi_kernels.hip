@@ -203,9 +203,10 @@ struct TileMap {
 template <int KM, int NB, int PB>
 __global__ __launch_bounds__(64, 2) void search_kernel(
     const float2 *__restrict__ planes, int n_img, int h, int w,
-    const int2 *__restrict__ disp, const int32_t *__restrict__ vel_index, int n_vel,
-    int k_cand, TileMap tiles, float *__restrict__ cand_nu, float *__restrict__ cand_alpha,
-    int32_t *__restrict__ cand_vel, int16_t *__restrict__ cand_nobs) {
+    const int2 *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
+    int n_vel, int k_cand, TileMap tiles, float *__restrict__ cand_nu,
+    float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
+    int16_t *__restrict__ cand_nobs) {
     constexpr int kLdsWords = (3 * PB > KM ? 3 * PB : KM) * 64;
     __shared__ uint32_t lds[kLdsWords];
     uint32_t *q_hi = lds;
@@ -229,26 +230,31 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     uint64_t thr = 0;   // admission threshold (list tail at the last merge)
     int nq = 0;         // queued candidates of this lane
 
-    // Issue the loads of images [i0, i0 + NB) of visited velocity jj.  Slots
-    // past the last image, and rows outside the frame, get a zero-length
-    // buffer: their loads return 0 and add nothing, with no branch.
+    // Issue the loads of images [i0, i0 + NB) of visited velocity jj.  The
+    // table row is fetched whole first (its padding entries lie outside the
+    // frame); rows outside the frame get a zero-length buffer, so their loads
+    // return 0 and add nothing, with no branch.
+    const size_t img_bytes = img_stride * sizeof(float2);
     auto issue = [&](int jj, int i0, u32x2(&v)[NB]) {
-        const int2 *dj = disp + (size_t)jj * n_img;
-        // Recomputed per velocity (not hoisted): keeps 2 * NB image bases out
-        // of the scalar register file.
-        const char *pbase = reinterpret_cast<const char *>(planes);
+        const int4 *t4 = reinterpret_cast<const int4 *>(disp + (size_t)jj * disp_stride + i0);
+        int4 dd[NB / 2];
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) dd[q] = t4[q];
+        // Recomputed per velocity (not hoisted): keeps NB image bases out of
+        // the scalar register file.
+        const char *pbase = reinterpret_cast<const char *>(planes) + (size_t)i0 * img_bytes;
         asm volatile("" : "+s"(pbase));
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int i = i0 + b;
-            const bool have = i < n_img;
-            const int2 d = dj[have ? i : 0];
-            const int yy = row + d.y;
-            const bool in_rows = have && (unsigned)yy < (unsigned)h;
-            const size_t off = ((size_t)(have ? i : 0) * img_stride +
-                                (size_t)(in_rows ? yy : 0) * (size_t)w) * sizeof(float2);
-            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(pbase + off, in_rows ? row_bytes : 0u);
-            v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + d.x) * 8, 0, 0);
+            const int dx = (b & 1) ? dd[b / 2].z : dd[b / 2].x;
+            const int dy = (b & 1) ? dd[b / 2].w : dd[b / 2].y;
+            const int yy = row + dy;
+            const bool in_rows = (unsigned)yy < (unsigned)h;
+            const char *rb = pbase + (size_t)b * img_bytes +
+                             (size_t)(in_rows ? yy : 0) * (size_t)row_bytes;
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(in_rows ? rb : pbase,
+                                                          in_rows ? row_bytes : 0u);
+            v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + dx) * 8, 0, 0);
         }
     };
     // Sum in image order.  Empty slots hold +0, which leaves every sum unchanged.
@@ -293,9 +299,9 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     // and queue it if it beats the admission threshold.  n_obs only sits in
     // the low bits of the key and never decides an order, so it is counted
     // only for queued candidates.
-    auto finish = [&](int jj, float P, float F, uint32_t c) {
+    auto finish = [&](int j, float P, float F, uint32_t c) {
         const float nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
-        const uint64_t nk = make_key(nu, vel_index[jj], 0u);
+        const uint64_t nk = make_key(nu, j, 0u);
         if (nk > thr) {
             q_hi[nq * 64 + lane] = (uint32_t)(nk >> 32);
             q_lo[nq * 64 + lane] = (uint32_t)nk | c;
@@ -307,14 +313,16 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
 
     if (n_img <= NB) {
         for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = vel_index[jj];   // fetched before the gathers are issued
             u32x2 v[NB];
             issue(jj, 0, v);
             float P = 0.f, F = 0.f;
             accumulate(v, P, F);
-            finish(jj, P, F, count(v));
+            finish(j, P, F, count(v));
         }
     } else {
         for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = vel_index[jj];
             float P = 0.f, F = 0.f;
             uint32_t c = 0;
             for (int i0 = 0; i0 < n_img; i0 += NB) {
@@ -323,7 +331,7 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
                 accumulate(v, P, F);
                 c += count(v);
             }
-            finish(jj, P, F, c);
+            finish(j, P, F, c);
         }
     }
     merge_queue();
@@ -444,6 +452,8 @@ template <int KM, int NB>
 kb_status launch_search_nb(const float2 *planes, int n_img, int h, int w, const int2 *disp,
                            const int32_t *vel_index, int n_vel, int k_cand, float *cn, float *ca,
                            int32_t *cv, int16_t *co, hipStream_t stream) {
+    static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
+    const int stride = (int)table_stride(n_img);
     constexpr int PB = KBMI_QUEUE;
     TileMap tm;
     tm.nseg = (w + 63) / 64;
@@ -451,7 +461,8 @@ kb_status launch_search_nb(const float2 *planes, int n_img, int h, int w, const 
     tm.strip = tm.nseg < KBMI_STRIP_TILES ? tm.nseg : KBMI_STRIP_TILES;
     tm.nblocks = tm.nseg * h;
     hipLaunchKernelGGL((search_kernel<KM, NB, PB>), dim3(tm.nblocks), dim3(64), 0, stream,
-                       planes, n_img, h, w, disp, vel_index, n_vel, k_cand, tm, cn, ca, cv, co);
+                       planes, n_img, h, w, disp, stride, vel_index, n_vel, k_cand, tm, cn, ca,
+                       cv, co);
     return launch_status("search_kernel");
 }
 
@@ -476,6 +487,13 @@ kb_status launch_topk_km(int64_t npix, int k_cand, int k, const float *cn, const
     return launch_status("topk_kernel");
 }
 
+// List lengths compiled for the search: every even length up to KB_MAX_KCAND
+// (each slot costs registers and compare-and-swap work on every insertion).
+#define KB_SEARCH_KM_LIST(X)                                                              \
+    X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) \
+    X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50) X(52) X(54) X(56) X(58)  \
+    X(60) X(62) X(64)
+
 #define KB_DISPATCH_KM(kc, FN, ...)                  \
     ((kc) <= 8    ? FN<8>(__VA_ARGS__)               \
      : (kc) <= 16 ? FN<16>(__VA_ARGS__)              \
@@ -491,7 +509,7 @@ kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
         return fail(KB_EINVAL, "n_img must be in [1, 32767] (got %lld)", (long long)n_img);
     if (h < 1 || w < 1) return fail(KB_EINVAL, "h and w must be >= 1");
     if (w > (int64_t(1) << 27)) return fail(KB_EINVAL, "w must be <= 2^27");
-    if (h > 2147483647LL) return fail(KB_EINVAL, "h must be < 2^31");
+    if (h > (int64_t(1) << 30)) return fail(KB_EINVAL, "h must be <= 2^30");
     const int64_t nseg = (w + 63) / 64;
     if (nseg * h > 2147483647LL) return fail(KB_EINVAL, "frame too large for one launch");
     return KB_OK;
@@ -509,8 +527,17 @@ kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_
         vel_visit[2 * j] = vel[2 * order[j]];
         vel_visit[2 * j + 1] = vel[2 * order[j] + 1];
     }
-    std::vector<int32_t> table(static_cast<size_t>(n_img) * n_vel * 2);
-    displacement_table(t, n_img, vel_visit.data(), n_vel, table.data(), w, h);
+    std::vector<int32_t> dense(static_cast<size_t>(n_img) * n_vel * 2);
+    displacement_table(t, n_img, vel_visit.data(), n_vel, dense.data(), w, h);
+    // Pad each row to the stride with (0, h): row + h is outside the frame.
+    const int64_t stride = table_stride(n_img);
+    std::vector<int32_t> table(static_cast<size_t>(stride) * n_vel * 2);
+    for (int64_t j = 0; j < n_vel; ++j)
+        for (int64_t i = 0; i < stride; ++i) {
+            const bool real = i < n_img;
+            table[(j * stride + i) * 2] = real ? dense[(j * n_img + i) * 2] : 0;
+            table[(j * stride + i) * 2 + 1] = real ? dense[(j * n_img + i) * 2 + 1] : (int32_t)h;
+        }
     char *ws = static_cast<char *>(workspace);
     hipError_t e = hipMemcpyAsync(ws, table.data(), table.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, stream);
@@ -599,9 +626,17 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     const int kc = (int)k_cand;
     const int32_t *vel_index = reinterpret_cast<const int32_t *>(
         static_cast<const char *>(workspace) + table_bytes(n_img, n_vel));
-    return KB_DISPATCH_KM(kc, launch_search_km, reinterpret_cast<const float2 *>(planes),
-                          (int)n_img, (int)h, (int)w, reinterpret_cast<const int2 *>(workspace),
-                          vel_index, (int)n_vel, kc, cand_nu, cand_alpha, cand_vel, cand_nobs, s);
+    const int km = (kc + 1) & ~1;
+    switch (km) {
+#define KB_SEARCH_CASE(K)                                                                      \
+    case K:                                                                                    \
+        return launch_search_km<K>(reinterpret_cast<const float2 *>(planes), (int)n_img, (int)h, \
+                                   (int)w, reinterpret_cast<const int2 *>(workspace), vel_index, \
+                                   (int)n_vel, kc, cand_nu, cand_alpha, cand_vel, cand_nobs, s);
+        KB_SEARCH_KM_LIST(KB_SEARCH_CASE)
+#undef KB_SEARCH_CASE
+    }
+    return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
 }
 
 kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
