@@ -128,7 +128,7 @@ def main():
     planes = torch.empty((n, h, w, 2), dtype=torch.float32, device=dev)
     cand = lib.alloc_candidates(h, w, s.k, dev)
     res = lib.alloc_candidates(h, w, s.k, dev)
-    ws = lib.alloc_workspace(n, nv, dev)
+    ws = lib.alloc_workspace(n, h, w, nv, dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     log("inputs resident on the device")

@@ -102,14 +102,17 @@ kb_status kb_displacements(const double *t, int64_t n_img, const double *vel,
  *   psi_phi   device out, float32 [n_img][h][w][2]: (psi, phi) interleaved.
  *             A valid pixel whose phi is +0 is stored with phi = -0.0 so that
  *             the stored bit pattern of phi is nonzero exactly at valid pixels.
- *   lp_dtype  KB_F32 = no low-precision copy.  KB_F16 / KB_BF16 also write
- *             psi_phi_lp (device, 16-bit [n_img][h][w][2]) holding
- *             round-to-nearest(value * scale) with per-image, per-plane
- *             power-of-two scales written to lp_scale (device, float32
- *             [n_img][2]); not implemented in ABI version 1
- *             (KB_EUNSUPPORTED).
- * Errors: KB_EINVAL for null required pointers, n_img < 1, h < 1, w < 1,
- * even PSF sizes; KB_EUNSUPPORTED for a PSF side > KB_MAX_PSF.
+ *   lp_dtype  KB_F32 = no 16-bit copy.  KB_F16 / KB_BF16 also write
+ *             psi_phi_lp (device, 16-bit [n_img][h][w][2] pairs) holding
+ *             round-to-nearest-even(value * s) with one power-of-two scale s
+ *             per image and plane, chosen so that max|value| * s lies in
+ *             [2^13, 2^14), written to lp_scale (device, float32 [n_img][2]:
+ *             s_psi, s_phi).  A valid pixel whose scaled phi rounds to +0
+ *             stores -0, so the phi half is nonzero exactly at valid pixels.
+ *             The 16-bit copy only ranks; kb_topk re-scores from float32.
+ * Errors: KB_EINVAL for null required pointers (psi_phi_lp and lp_scale with
+ * a 16-bit lp_dtype), n_img < 1, h < 1, w < 1, even PSF sizes or an unknown
+ * lp_dtype; KB_EUNSUPPORTED for a PSF side > KB_MAX_PSF.
  */
 kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mask,
                           int64_t n_img, int64_t h, int64_t w,
@@ -117,9 +120,10 @@ kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mas
                           float *psi_phi, int32_t lp_dtype, void *psi_phi_lp,
                           float *lp_scale, void *stream);
 
-/* Bytes of device workspace kb_search and kb_topk need (the displacement
- * table plus alignment). */
-size_t kb_search_workspace_bytes(int64_t n_img, int64_t n_vel);
+/* Bytes of device workspace kb_search and kb_topk need for a stack of n_img
+ * frames of h x w and n_vel velocities (displacement table, visiting order,
+ * 16-bit scales); 0 for invalid sizes. */
+size_t kb_search_workspace_bytes(int64_t n_img, int64_t h, int64_t w, int64_t n_vel);
 
 /*
  * kb_search - exhaustive evaluation of every (start pixel, velocity) pair
@@ -132,23 +136,25 @@ size_t kb_search_workspace_bytes(int64_t n_img, int64_t n_vel);
  * alpha = Psi/Phi; otherwise nu = -inf, alpha = 0.  For every start pixel the
  * k_cand best trajectories in the order (nu descending, velocity index
  * ascending) are kept.
- *   planes     device, [n_img][h][w][2] pairs as written by kb_make_psi_phi,
- *              of type `dtype` (only KB_F32 in ABI version 1).
+ *   planes     device, [n_img][h][w][2] pairs as written by kb_make_psi_phi:
+ *              float32 (dtype KB_F32) or its scaled 16-bit copy (KB_F16,
+ *              KB_BF16; each value is decoded and multiplied by 1/s, exactly,
+ *              before it is summed in float32).
  *   lp_scale   device float32 [n_img][2] for 16-bit planes; NULL for KB_F32.
  *   t, vel     host, as for kb_displacements.
  *   k_cand     1 <= k_cand <= min(n_vel, KB_MAX_KCAND).
  *   cand_nu, cand_alpha  device out, float32 [h][w][k_cand].
  *   cand_vel   device out, int32 [h][w][k_cand]: velocity index j.
  *   cand_nobs  device out, int16 [h][w][k_cand]: n_obs.
- *              Each pixel's k_cand entries are the best set; their order
- *              within a pixel is unspecified (kb_topk orders them).
- *   workspace  device, >= kb_search_workspace_bytes(n_img, n_vel) bytes,
- *              256-byte aligned; overwritten.
+ *              Each pixel's k_cand entries are the best set, written in rank
+ *              order (kb_topk accepts them in any order).
+ *   workspace  device, >= kb_search_workspace_bytes(n_img, h, w, n_vel)
+ *              bytes, 256-byte aligned; overwritten.
  * Limits: n_img <= 32767, n_vel <= 65535, w <= 2^27, h <= 2^31 - 1.
  * The displacement table is copied host-to-device on `stream`; from pageable
  * memory that copy may wait for earlier work on the stream.
  * Errors: KB_EINVAL for bad sizes, pointers or times; KB_ENOMEM for a short
- * workspace; KB_EUNSUPPORTED for k_cand > KB_MAX_KCAND or 16-bit planes.
+ * workspace; KB_EUNSUPPORTED for k_cand > KB_MAX_KCAND.
  */
 kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale,
                     int64_t n_img, int64_t h, int64_t w,
@@ -163,13 +169,18 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale,
  * k (Sec. 2.2 asks for the trajectories maximising nu).
  *   psi_phi_f32  device float32 planes [n_img][h][w][2] to re-score every
  *                candidate from before ordering (used after a 16-bit search),
- *                or NULL to keep the candidates' scores.  Re-scoring is not
- *                implemented in ABI version 1 (KB_EUNSUPPORTED).
+ *                or NULL to keep the candidates' scores.  A re-scored entry
+ *                is computed with exactly the float32 search's arithmetic
+ *                (image order, same score expressions), so it equals the
+ *                plain path's value for that trajectory bit for bit.
  *   t, vel, n_vel, workspace  as for kb_search (used only when re-scoring).
- *   cand_*       device, as written by kb_search.
- *   nu, alpha, vel_idx, nobs  device out, [h][w][k] in rank order.
- * Errors: KB_EINVAL for bad sizes or pointers or k > k_cand; KB_EUNSUPPORTED
- * for k_cand > KB_MAX_KCAND.
+ *   cand_*       device, as written by kb_search (any order within a pixel;
+ *                with re-scoring only cand_vel is read).
+ *   nu, alpha, vel_idx, nobs  device out, [h][w][k] in rank order; must not
+ *                overlap the candidate arrays.
+ * Errors: KB_EINVAL for bad sizes or pointers, k > k_cand, or (re-scoring)
+ * bad times/velocities or workspace; KB_ENOMEM for a short workspace;
+ * KB_EUNSUPPORTED for k_cand > KB_MAX_KCAND.
  */
 kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
                   const double *t, const double *vel, int64_t n_vel,

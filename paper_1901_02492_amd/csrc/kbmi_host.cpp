@@ -132,6 +132,19 @@ size_t order_bytes(int64_t n_vel) {
 
 int64_t table_stride(int64_t n_img) { return n_img <= 8 ? 8 : (n_img + 15) / 16 * 16; }
 
+static size_t align256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
+
+WorkspaceLayout workspace_layout(int64_t n_img, int64_t h, int64_t w, int64_t n_vel) {
+    WorkspaceLayout l;
+    l.table = 0;
+    l.order = l.table + table_bytes(n_img, n_vel);
+    l.inv_scale = l.order + order_bytes(n_vel);
+    l.total = l.inv_scale + align256(static_cast<size_t>(table_stride(n_img)) * 8);
+    (void)h;
+    (void)w;
+    return l;
+}
+
 size_t table_bytes(int64_t n_img, int64_t n_vel) {
     const size_t raw = static_cast<size_t>(table_stride(n_img)) * static_cast<size_t>(n_vel) * 2 *
                        sizeof(int32_t);
@@ -156,9 +169,9 @@ kb_status kb_displacements(const double *t, int64_t n_img, const double *vel, in
     return KB_OK;
 }
 
-size_t kb_search_workspace_bytes(int64_t n_img, int64_t n_vel) {
-    if (n_img < 1 || n_vel < 1) return 0;
-    return kbmi::table_bytes(n_img, n_vel) + kbmi::order_bytes(n_vel);
+size_t kb_search_workspace_bytes(int64_t n_img, int64_t h, int64_t w, int64_t n_vel) {
+    if (n_img < 1 || n_vel < 1 || h < 1 || w < 1) return 0;
+    return kbmi::workspace_layout(n_img, h, w, n_vel).total;
 }
 
 }  // extern "C"

@@ -39,5 +39,12 @@ void velocity_order(const double *vel, int64_t n_vel, int32_t *order);
 int64_t table_stride(int64_t n_img);
 size_t table_bytes(int64_t n_img, int64_t n_vel);
 size_t order_bytes(int64_t n_vel);
+// Whole workspace of kb_search / kb_topk (byte offsets, 256-byte aligned): the
+// table, the visiting order and the 16-bit search's per-image inverse scales
+// (float2 [table_stride]).
+struct WorkspaceLayout {
+    size_t table, order, inv_scale, total;
+};
+WorkspaceLayout workspace_layout(int64_t n_img, int64_t h, int64_t w, int64_t n_vel);
 
 }  // namespace kbmi

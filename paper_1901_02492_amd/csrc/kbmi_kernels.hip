@@ -16,6 +16,7 @@
 // positions add exactly +0 and count nothing, without per-lane branches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -61,7 +62,7 @@ constexpr int PP_LH = PP_TH + KB_MAX_PSF - 1;
 __global__ __launch_bounds__(PP_THREADS) void psi_phi_kernel(
     const float *__restrict__ img, const float *__restrict__ var,
     const uint8_t *__restrict__ mask, int h, int w, int ph, int pw, PsfTaps psf,
-    float2 *__restrict__ out) {
+    float2 *__restrict__ out, uint32_t *__restrict__ maxabs) {
     __shared__ float s_a[PP_LH * PP_LW];
     __shared__ float s_w[PP_LH * PP_LW];
     __shared__ uint8_t s_ok[PP_LH * PP_LW];
@@ -122,6 +123,96 @@ __global__ __launch_bounds__(PP_THREADS) void psi_phi_kernel(
             }
             out[plane + (size_t)gy * w + gx] = res;
         }
+    }
+    if (maxabs != nullptr) {
+        // Per-image max |psi| and max phi for the 16-bit copy's scale: a block
+        // reduction, then one atomic max per block and plane (non-negative
+        // floats order like their bit patterns).
+        __shared__ float s_red[2][PP_THREADS / 64];
+        float mp = 0.f, mf = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gy = ty0 + ly0 + 4 * r, gx = tx0 + lx;
+            if (gy < h && gx < w && s_ok[(ly0 + 4 * r + cy) * PP_LW + lx + cx]) {
+                mp = fmaxf(mp, fabsf(ps[r]));
+                mf = fmaxf(mf, pf[r]);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            mp = fmaxf(mp, __shfl_xor(mp, off));
+            mf = fmaxf(mf, __shfl_xor(mf, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            s_red[0][threadIdx.x / 64] = mp;
+            s_red[1][threadIdx.x / 64] = mf;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            float m = 0.f;
+#pragma unroll
+            for (int q = 0; q < PP_THREADS / 64; ++q) m = fmaxf(m, s_red[threadIdx.x][q]);
+            atomicMax(&maxabs[2 * i + threadIdx.x], __float_as_uint(m));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit plane copies.  Per image and plane the scale is the power of two s
+// with max|value| * s in [2^13, 2^14): the scaled values keep FP16's full
+// precision and stay far below its overflow.  Stored value = RNE(value * s);
+// a valid pixel whose scaled phi rounds to +0 stores -0 so that the phi bits
+// stay nonzero exactly at valid pixels.  The search multiplies by 1/s, which
+// is exact.
+// ---------------------------------------------------------------------------
+__global__ void lp_zero_kernel(uint32_t *__restrict__ maxabs, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) maxabs[t] = 0u;
+}
+
+__global__ void lp_scale_kernel(float *__restrict__ scale, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        const float m = scale[t];   // max |value| (stored through its bit pattern)
+        float sc = 1.f;
+        if (m > 0.f && isfinite(m)) {
+            int e;
+            frexpf(m, &e);                       // m = f * 2^e, f in [0.5, 1)
+            int x = 14 - e;
+            x = x < -126 ? -126 : (x > 127 ? 127 : x);
+            sc = ldexpf(1.f, x);
+        }
+        scale[t] = sc;
+    }
+}
+
+__device__ inline uint16_t to_lp(float v, int fmt) {
+    if (fmt == KB_F16) {
+        const _Float16 hv = (_Float16)v;            // round to nearest even
+        return __builtin_bit_cast(uint16_t, hv);
+    }
+    // bfloat16, round to nearest even (inputs are finite)
+    const uint32_t u = __float_as_uint(v);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ __launch_bounds__(256) void lp_convert_kernel(
+    const float2 *__restrict__ planes, size_t npix_img, const float *__restrict__ scale, int fmt,
+    uint32_t *__restrict__ out) {
+    const int i = blockIdx.y;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < npix_img;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const size_t e = (size_t)i * npix_img + q;
+        const float2 v = planes[e];
+        const uint32_t fbits = __float_as_uint(v.y);
+        uint32_t packed = 0u;
+        if (fbits != 0u) {                            // valid pixel
+            const uint16_t hp = to_lp(v.x * scale[2 * i], fmt);
+            uint16_t hf = to_lp(v.y * scale[2 * i + 1], fmt);
+            if ((hf & 0x7FFFu) == 0u) hf = 0x8000u;   // keep the validity bit pattern
+            packed = (uint32_t)hp | ((uint32_t)hf << 16);
+        }
+        out[e] = packed;
     }
 }
 
@@ -200,10 +291,63 @@ struct TileMap {
 // is bounded to two waves per SIMD: memory-level parallelism comes from the
 // waves, each holding one velocity's NB loads in flight.
 // ---------------------------------------------------------------------------
-template <int KM, int NB, int PB>
+template <int FMT>
+struct PlaneLoad {                       // one (psi, phi) pair as loaded
+    typedef u32x2 type;                  // float32: two words
+};
+template <>
+struct PlaneLoad<KB_F16> {
+    typedef uint32_t type;               // 16-bit: psi low half, phi high half
+};
+template <>
+struct PlaneLoad<KB_BF16> {
+    typedef uint32_t type;
+};
+
+__device__ inline float lp_value(uint32_t bits16, int fmt) {
+    if (fmt == KB_F16) return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+    return __uint_as_float(bits16 << 16);
+}
+
+// One search problem as the host launchers see it.
+struct StackView {
+    const void *planes;        // [n_img][h][w] (psi, phi) pairs of format FMT
+    const float2 *inv_scale;   // 16-bit planes: (1/s_psi, 1/s_phi) per image, padded with 0
+    int n_img, h, w;
+    const int2 *disp;          // displacement rows in visiting order, `disp_stride` pairs each
+    int disp_stride;
+    const int32_t *vel_index;  // original index of each visited velocity
+    int n_vel, k_cand;
+    float *cand_nu, *cand_alpha;
+    int32_t *cand_vel;
+    int16_t *cand_nobs;
+};
+
+// ---------------------------------------------------------------------------
+// Trajectory search.
+//
+// One wave (one workgroup) owns 64 adjacent start pixels of one row and walks
+// every velocity in the host-chosen visiting order.  Per velocity each lane
+// gathers its trajectory's N (psi, phi) pairs (one coalesced 512-byte run per
+// image across the wave), sums them in image order and scores nu.
+//
+// Per-pixel selection keeps a descending list of KM >= k_cand keys in
+// registers.  Inserting into it costs a compare-and-swap per slot, and the wave
+// pays for it whenever any lane inserts, so candidates are first filtered
+// against a per-lane threshold (the list's last key at the last merge) and
+// parked in a per-lane LDS queue of PB entries; the queue is merged into the
+// list only when some lane's queue is full (and at the end).  A candidate that
+// fails the threshold can never enter the final list: the threshold only rises.
+//
+// The loads of up to NB images are issued together before they are summed in
+// image order; larger stacks are summed in batches of NB images.  The kernel
+// is bounded to two waves per SIMD: memory-level parallelism comes from the
+// waves, each holding one velocity's NB loads in flight.
+// ---------------------------------------------------------------------------
+template <int KM, int NB, int PB, int FMT>
 __global__ __launch_bounds__(64, 2) void search_kernel(
-    const float2 *__restrict__ planes, int n_img, int h, int w,
-    const int2 *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
+    const void *__restrict__ planes, const float2 *__restrict__ inv_scale, int n_img, int h,
+    int w, const int2 *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
     int n_vel, int k_cand, TileMap tiles, float *__restrict__ cand_nu,
     float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
     int16_t *__restrict__ cand_nobs) {
@@ -217,8 +361,10 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     int row, seg;
     tiles.map(blockIdx.x, row, seg);
     const int x0 = seg * 64 + lane;
-    const uint32_t row_bytes = (uint32_t)w * 8u;
-    const size_t img_stride = (size_t)h * (size_t)w;
+    typedef typename PlaneLoad<FMT>::type LoadT;
+    constexpr uint32_t kPix = FMT == KB_F32 ? 8u : 4u;   // bytes per (psi, phi) pair
+    const uint32_t row_bytes = (uint32_t)w * kPix;
+    const size_t img_bytes = (size_t)h * (size_t)w * kPix;
 
     uint64_t key[KM];
     float al[KM];
@@ -234,8 +380,7 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     // table row is fetched whole first (its padding entries lie outside the
     // frame); rows outside the frame get a zero-length buffer, so their loads
     // return 0 and add nothing, with no branch.
-    const size_t img_bytes = img_stride * sizeof(float2);
-    auto issue = [&](int jj, int i0, u32x2(&v)[NB]) {
+    auto issue = [&](int jj, int i0, LoadT(&v)[NB]) {
         const int4 *t4 = reinterpret_cast<const int4 *>(disp + (size_t)jj * disp_stride + i0);
         int4 dd[NB / 2];
 #pragma unroll
@@ -254,22 +399,45 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
                              (size_t)(in_rows ? yy : 0) * (size_t)row_bytes;
             const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(in_rows ? rb : pbase,
                                                           in_rows ? row_bytes : 0u);
-            v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + dx) * 8, 0, 0);
+            if constexpr (FMT == KB_F32)
+                v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + dx) * (int)kPix, 0, 0);
+            else
+                v[b] = __builtin_amdgcn_raw_buffer_load_b32(rs, (x0 + dx) * (int)kPix, 0, 0);
         }
     };
-    // Sum in image order.  Empty slots hold +0, which leaves every sum unchanged.
-    auto accumulate = [&](const u32x2(&v)[NB], float &P, float &F) {
+    // Sum in image order.  Empty slots hold +0, which leaves every sum
+    // unchanged.  16-bit values are decoded and unscaled by an exact power of
+    // two inside the FMA (the product is exact, so the sum rounds once).
+    auto accumulate = [&](int i0, const LoadT(&v)[NB], float &P, float &F) {
+        if constexpr (FMT == KB_F32) {
+            (void)i0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            P += __uint_as_float(v[b].x);
-            F += __uint_as_float(v[b].y);
+            for (int b = 0; b < NB; ++b) {
+                P += __uint_as_float(v[b].x);
+                F += __uint_as_float(v[b].y);
+            }
+        } else {
+            const float4 *sc4 = reinterpret_cast<const float4 *>(inv_scale + i0);
+            float4 ss[NB / 2];
+#pragma unroll
+            for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float isp = (b & 1) ? ss[b / 2].z : ss[b / 2].x;
+                const float isf = (b & 1) ? ss[b / 2].w : ss[b / 2].y;
+                P = fmaf(lp_value(v[b] & 0xFFFFu, FMT), isp, P);
+                F = fmaf(lp_value(v[b] >> 16, FMT), isf, F);
+            }
         }
     };
-    // n_obs: stored phi is nonzero exactly at valid pixels; empty slots are 0.
-    auto count = [&](const u32x2(&v)[NB]) {
+    // n_obs: the stored phi is nonzero exactly at valid pixels; empty slots are 0.
+    auto count = [&](const LoadT(&v)[NB]) {
         uint32_t c = 0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) c += v[b].y != 0u;
+        for (int b = 0; b < NB; ++b) {
+            if constexpr (FMT == KB_F32) c += v[b].y != 0u;
+            else c += (v[b] >> 16) != 0u;
+        }
         return c;
     };
     auto insert = [&](uint64_t nk, float a) {
@@ -296,9 +464,8 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
         thr = key[KM - 1];
     };
     // Score one trajectory (Sec. 2.1.5: nu = Psi / sqrt(Phi), alpha = Psi / Phi)
-    // and queue it if it beats the admission threshold.  n_obs only sits in
-    // the low bits of the key and never decides an order, so it is counted
-    // only for queued candidates.
+    // and queue it if it beats the admission threshold.  n_obs sits in the
+    // low bits of the key and never decides an order.
     auto finish = [&](int j, float P, float F, uint32_t c) {
         const float nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
         const uint64_t nk = make_key(nu, j, 0u);
@@ -314,10 +481,10 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     if (n_img <= NB) {
         for (int jj = 0; jj < n_vel; ++jj) {
             const int j = vel_index[jj];   // fetched before the gathers are issued
-            u32x2 v[NB];
+            LoadT v[NB];
             issue(jj, 0, v);
             float P = 0.f, F = 0.f;
-            accumulate(v, P, F);
+            accumulate(0, v, P, F);
             finish(j, P, F, count(v));
         }
     } else {
@@ -326,9 +493,9 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
             float P = 0.f, F = 0.f;
             uint32_t c = 0;
             for (int i0 = 0; i0 < n_img; i0 += NB) {
-                u32x2 v[NB];
+                LoadT v[NB];
                 issue(jj, i0, v);
-                accumulate(v, P, F);
+                accumulate(i0, v, P, F);
                 c += count(v);
             }
             finish(j, P, F, c);
@@ -370,71 +537,118 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Final selection.  One wave handles 64 consecutive pixels: their candidate
-// runs are loaded with coalesced reads into LDS, each lane checks that its
-// pixel's candidates are in rank order (kb_search leaves them so), and the
-// first k of every pixel are written back with coalesced stores.  A pixel
-// whose candidates are not in order is ranked by counting, for each
-// candidate, the candidates that precede it.
+// Final selection.  One thread per candidate: a 256-thread block holds whole
+// pixels (256 / k_cand of them), reads their candidate runs with coalesced
+// loads, and each thread checks that its candidate precedes the next one of
+// the same pixel.  When every pixel of the block is in rank order (kb_search
+// leaves them so) the first k of each are copied out; otherwise each
+// candidate's rank is the number of candidates of its pixel that precede it.
 // ---------------------------------------------------------------------------
-template <int KM>
-__global__ __launch_bounds__(64) void topk_kernel(
+constexpr int TK_THREADS = 256;
+
+__global__ __launch_bounds__(TK_THREADS) void topk_kernel(
     int64_t npix, int k_cand, int k, const float *__restrict__ cand_nu,
     const float *__restrict__ cand_alpha, const int32_t *__restrict__ cand_vel,
     const int16_t *__restrict__ cand_nobs, float *__restrict__ nu, float *__restrict__ alpha,
     int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
-    __shared__ uint32_t s_nu[64 * KM], s_al[64 * KM], s_vel[64 * KM];
-    __shared__ uint16_t s_no[64 * KM];
-    __shared__ uint8_t s_rank[64 * KM];
-    const int lane = (int)threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.x * 64;
-    const int npx = (npix - p0) < 64 ? (int)(npix - p0) : 64;
-    const int total = npx * k_cand;
-    const size_t ib = (size_t)p0 * (size_t)k_cand;
-    for (int idx = lane; idx < total; idx += 64) {
-        s_nu[idx] = __float_as_uint(cand_nu[ib + idx]);
-        s_al[idx] = __float_as_uint(cand_alpha[ib + idx]);
-        s_vel[idx] = (uint32_t)cand_vel[ib + idx];
-        s_no[idx] = (uint16_t)cand_nobs[ib + idx];
+    __shared__ uint64_t s_key[TK_THREADS];
+    const int ppb = TK_THREADS / k_cand;
+    const int t = (int)threadIdx.x;
+    const int lp = t / k_cand, s = t - lp * k_cand;
+    const int64_t p = (int64_t)blockIdx.x * ppb + lp;
+    const bool active = lp < ppb && p < npix;
+    uint64_t key = 0;
+    float v_nu = 0.f, v_al = 0.f;
+    int32_t v_vel = 0;
+    int16_t v_no = 0;
+    if (active) {
+        const size_t e = (size_t)p * (size_t)k_cand + (size_t)s;
+        v_nu = cand_nu[e];
+        v_al = cand_alpha[e];
+        v_vel = cand_vel[e];
+        v_no = cand_nobs[e];
+        key = make_key(v_nu, v_vel, (uint16_t)v_no);
     }
+    s_key[t] = key;
     __syncthreads();
-    auto key_at = [&](int idx) {
-        return make_key(__uint_as_float(s_nu[idx]), (int)s_vel[idx], s_no[idx]);
-    };
-    bool ordered = true;
-    if (lane < npx) {
-        const int o = lane * k_cand;
-        uint64_t prev = key_at(o);
-        for (int s = 1; s < k_cand; ++s) {
-            const uint64_t cur = key_at(o + s);
-            ordered = ordered && prev > cur;
-            prev = cur;
-        }
+    const bool out_of_order = active && s + 1 < k_cand && !(key > s_key[t + 1]);
+    int rank = s;
+    if (__syncthreads_or(out_of_order)) {
+        rank = 0;
+        for (int r = 0; r < k_cand; ++r) rank += s_key[lp * k_cand + r] > key;
     }
-    if (__all(ordered)) {
-        for (int idx = lane; idx < total; idx += 64) s_rank[idx] = (uint8_t)(idx % k_cand);
-    } else if (lane < npx) {
-        const int o = lane * k_cand;
-        for (int s = 0; s < k_cand; ++s) {
-            const uint64_t ks = key_at(o + s);
-            int r = 0;
-            for (int t = 0; t < k_cand; ++t) r += key_at(o + t) > ks;
-            s_rank[o + s] = (uint8_t)r;
-        }
+    if (active && rank < k) {
+        const size_t o = (size_t)p * (size_t)k + (size_t)rank;
+        nu[o] = v_nu;
+        alpha[o] = v_al;
+        vel[o] = v_vel;
+        nobs[o] = v_no;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Re-scoring selection (after a 16-bit search): every candidate's Psi, Phi and
+// n_obs are recomputed from the float32 planes with exactly the arithmetic of
+// the float32 search (image order, out-of-frame terms adding +0, the same
+// score expressions), so a re-scored entry is bitwise the plain path's value
+// for that trajectory.  Then every pixel's candidates are ranked by counting.
+// table: displacements in the original velocity order, rows of `stride`.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
+    int64_t npix, int h, int w, int n_img, const float2 *__restrict__ planes,
+    const int2 *__restrict__ table, int stride, int n_vel, int k_cand, int k,
+    const int32_t *__restrict__ cand_vel, float *__restrict__ nu, float *__restrict__ alpha,
+    int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
+    __shared__ uint64_t s_key[TK_THREADS];
+    const int ppb = TK_THREADS / k_cand;
+    const int t = (int)threadIdx.x;
+    const int lp = t / k_cand;
+    const int64_t p = (int64_t)blockIdx.x * ppb + lp;
+    const bool active = lp < ppb && p < npix;
+    uint64_t key = 0;
+    float v_nu = 0.f, v_al = 0.f;
+    int32_t j = 0;
+    uint32_t c = 0;
+    if (active) j = cand_vel[(size_t)p * (size_t)k_cand + (size_t)(t - lp * k_cand)];
+    // A candidate index outside the grid (not written by kb_search) is dropped.
+    const bool scored = active && j >= 0 && j < n_vel;
+    if (scored) {
+        const int y0 = (int)(p / w), x0 = (int)(p - (int64_t)y0 * w);
+        const int2 *tj = table + (size_t)j * (size_t)stride;
+        float P = 0.f, F = 0.f;
+        for (int i0 = 0; i0 < n_img; i0 += 8) {
+            float2 v[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int i = i0 + b;
+                const int2 d = tj[i < n_img ? i : 0];
+                const int y = y0 + d.y, x = x0 + d.x;
+                const bool ok = i < n_img && (unsigned)y < (unsigned)h && (unsigned)x < (unsigned)w;
+                const size_t idx = ok ? ((size_t)i * h + y) * (size_t)w + x : 0;
+                const float2 raw = planes[idx];
+                v[b] = ok ? raw : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                P += v[b].x;
+                F += v[b].y;
+                c += __float_as_uint(v[b].y) != 0u;
+            }
+        }
+        v_nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
+        v_al = F > 0.f ? P / F : 0.f;
+        key = make_key(v_nu, j, c);
+    }
+    s_key[t] = key;
     __syncthreads();
-    // Scatter into the output by rank; entries ranked >= k are dropped.  The
-    // writes of a wave cover the contiguous [npx][k] run.
-    const size_t ob = (size_t)p0 * (size_t)k;
-    for (int idx = lane; idx < total; idx += 64) {
-        const int r = s_rank[idx];
-        if (r < k) {
-            const size_t o = ob + (size_t)(idx / k_cand) * (size_t)k + (size_t)r;
-            nu[o] = __uint_as_float(s_nu[idx]);
-            alpha[o] = __uint_as_float(s_al[idx]);
-            vel[o] = (int32_t)s_vel[idx];
-            nobs[o] = (int16_t)s_no[idx];
-        }
+    int rank = 0;
+    for (int r = 0; r < k_cand; ++r) rank += s_key[lp * k_cand + r] > key;
+    if (active && rank < k) {
+        const size_t o = (size_t)p * (size_t)k + (size_t)rank;
+        nu[o] = scored ? v_nu : -INFINITY;
+        alpha[o] = v_al;
+        vel[o] = j;
+        nobs[o] = (int16_t)c;
     }
 }
 
@@ -448,41 +662,75 @@ kb_status launch_status(const char *what) {
     return KB_OK;
 }
 
-template <int KM, int NB>
-kb_status launch_search_nb(const float2 *planes, int n_img, int h, int w, const int2 *disp,
-                           const int32_t *vel_index, int n_vel, int k_cand, float *cn, float *ca,
-                           int32_t *cv, int16_t *co, hipStream_t stream) {
-    static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
-    const int stride = (int)table_stride(n_img);
-    constexpr int PB = KBMI_QUEUE;
+struct SearchLaunch {
+    StackView sv;
+    int fmt;
+    hipStream_t stream;
+};
+
+TileMap tile_map(int w, int h) {
     TileMap tm;
     tm.nseg = (w + 63) / 64;
     tm.h = h;
     tm.strip = tm.nseg < KBMI_STRIP_TILES ? tm.nseg : KBMI_STRIP_TILES;
     tm.nblocks = tm.nseg * h;
-    hipLaunchKernelGGL((search_kernel<KM, NB, PB>), dim3(tm.nblocks), dim3(64), 0, stream,
-                       planes, n_img, h, w, disp, stride, vel_index, n_vel, k_cand, tm, cn, ca,
-                       cv, co);
+    return tm;
+}
+
+template <int KM, int NB, int FMT>
+kb_status launch_search_fmt(const SearchLaunch &a) {
+    constexpr int PB = KBMI_QUEUE;
+    const StackView &v = a.sv;
+    const TileMap tm = tile_map(v.w, v.h);
+    hipLaunchKernelGGL((search_kernel<KM, NB, PB, FMT>), dim3(tm.nblocks), dim3(64), 0, a.stream,
+                       v.planes, v.inv_scale, v.n_img, v.h, v.w, v.disp, v.disp_stride,
+                       v.vel_index, v.n_vel, v.k_cand, tm, v.cand_nu, v.cand_alpha, v.cand_vel,
+                       v.cand_nobs);
     return launch_status("search_kernel");
 }
 
-template <int KM>
-kb_status launch_search_km(const float2 *planes, int n_img, int h, int w, const int2 *disp,
-                           const int32_t *vel_index, int n_vel, int k_cand, float *cn, float *ca,
-                           int32_t *cv, int16_t *co, hipStream_t stream) {
-    if (n_img <= 8)
-        return launch_search_nb<KM, 8>(planes, n_img, h, w, disp, vel_index, n_vel, k_cand, cn,
-                                       ca, cv, co, stream);
-    return launch_search_nb<KM, 16>(planes, n_img, h, w, disp, vel_index, n_vel, k_cand, cn, ca,
-                                    cv, co, stream);
+template <int KM, int NB>
+kb_status launch_search_nb(const SearchLaunch &a) {
+    static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
+    if (a.fmt == KB_F16) return launch_search_fmt<KM, NB, KB_F16>(a);
+    if (a.fmt == KB_BF16) return launch_search_fmt<KM, NB, KB_BF16>(a);
+    return launch_search_fmt<KM, NB, KB_F32>(a);
 }
 
 template <int KM>
-kb_status launch_topk_km(int64_t npix, int k_cand, int k, const float *cn, const float *ca,
-                         const int32_t *cv, const int16_t *co, float *nu, float *al,
-                         int32_t *vi, int16_t *no, hipStream_t stream) {
-    const int64_t blocks = (npix + 63) / 64;
-    hipLaunchKernelGGL((topk_kernel<KM>), dim3((unsigned)blocks), dim3(64), 0, stream, npix,
+kb_status launch_search_km(const SearchLaunch &a) {
+    if (a.sv.n_img <= 8) return launch_search_nb<KM, 8>(a);
+    return launch_search_nb<KM, 16>(a);
+}
+
+// 1/s per image and plane for the 16-bit search, padded with 0 to the table
+// stride (padding images then contribute exactly 0).
+__global__ void inv_scale_kernel(const float *__restrict__ scale, int n_img, int stride,
+                                 float2 *__restrict__ inv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < stride)
+        inv[i] = i < n_img ? make_float2(1.0f / scale[2 * i], 1.0f / scale[2 * i + 1])
+                           : make_float2(0.f, 0.f);
+}
+
+kb_status launch_topk_rescore(int64_t npix, int h, int w, int n_img, const float2 *planes,
+                              const int2 *table, int stride, int n_vel, int k_cand, int k,
+                              const int32_t *cv,
+                              float *nu, float *al, int32_t *vi, int16_t *no, hipStream_t stream) {
+    const int64_t ppb = TK_THREADS / k_cand;
+    const int64_t blocks = (npix + ppb - 1) / ppb;
+    hipLaunchKernelGGL(topk_rescore_kernel, dim3((unsigned)blocks), dim3(TK_THREADS), 0, stream,
+                       npix, h, w, n_img, planes, table, stride, n_vel, k_cand, k, cv, nu, al, vi,
+                       no);
+    return launch_status("topk_rescore_kernel");
+}
+
+kb_status launch_topk(int64_t npix, int k_cand, int k, const float *cn, const float *ca,
+                      const int32_t *cv, const int16_t *co, float *nu, float *al, int32_t *vi,
+                      int16_t *no, hipStream_t stream) {
+    const int64_t ppb = TK_THREADS / k_cand;
+    const int64_t blocks = (npix + ppb - 1) / ppb;
+    hipLaunchKernelGGL(topk_kernel, dim3((unsigned)blocks), dim3(TK_THREADS), 0, stream, npix,
                        k_cand, k, cn, ca, cv, co, nu, al, vi, no);
     return launch_status("topk_kernel");
 }
@@ -493,16 +741,6 @@ kb_status launch_topk_km(int64_t npix, int k_cand, int k, const float *cn, const
     X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) \
     X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50) X(52) X(54) X(56) X(58)  \
     X(60) X(62) X(64)
-
-#define KB_DISPATCH_KM(kc, FN, ...)                  \
-    ((kc) <= 8    ? FN<8>(__VA_ARGS__)               \
-     : (kc) <= 16 ? FN<16>(__VA_ARGS__)              \
-     : (kc) <= 24 ? FN<24>(__VA_ARGS__)              \
-     : (kc) <= 32 ? FN<32>(__VA_ARGS__)              \
-     : (kc) <= 40 ? FN<40>(__VA_ARGS__)              \
-     : (kc) <= 48 ? FN<48>(__VA_ARGS__)              \
-     : (kc) <= 56 ? FN<56>(__VA_ARGS__)              \
-                  : FN<64>(__VA_ARGS__))
 
 kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
     if (n_img < 1 || n_img > 32767)
@@ -518,10 +756,14 @@ kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
 // Copy the clamped displacement table into the workspace.  The host copy is
 // pageable and temporary, so the call waits until it has reached the device.
 kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
-                       int64_t h, int64_t w, void *workspace, hipStream_t stream) {
+                       int64_t h, int64_t w, void *workspace, hipStream_t stream,
+                       bool visiting_order = true) {
     // Velocities in visiting order, then the table of the reordered grid.
     std::vector<int32_t> order(static_cast<size_t>(n_vel));
-    velocity_order(vel, n_vel, order.data());
+    if (visiting_order)
+        velocity_order(vel, n_vel, order.data());
+    else
+        for (int64_t j = 0; j < n_vel; ++j) order[j] = static_cast<int32_t>(j);
     std::vector<double> vel_visit(static_cast<size_t>(n_vel) * 2);
     for (int64_t j = 0; j < n_vel; ++j) {
         vel_visit[2 * j] = vel[2 * order[j]];
@@ -576,18 +818,36 @@ kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mas
     if (lp_dtype != KB_F32) {
         if (lp_dtype != KB_F16 && lp_dtype != KB_BF16)
             return fail(KB_EINVAL, "lp_dtype must be KB_F32, KB_F16 or KB_BF16");
-        return fail(KB_EUNSUPPORTED, "16-bit plane copies are not implemented in this build");
+        if (!psi_phi_lp || !lp_scale)
+            return fail(KB_EINVAL, "a 16-bit copy needs psi_phi_lp and lp_scale");
     }
-    (void)psi_phi_lp;
-    (void)lp_scale;
     PsfTaps taps{};
     for (int64_t u = 0; u < psf_h * psf_w; ++u) taps.t[u] = psf[u];
     const dim3 grid((unsigned)((w + PP_TW - 1) / PP_TW), (unsigned)((h + PP_TH - 1) / PP_TH),
                     (unsigned)n_img);
-    hipLaunchKernelGGL(psi_phi_kernel, grid, dim3(PP_THREADS), 0, (hipStream_t)stream, img, var,
-                       mask, (int)h, (int)w, (int)psf_h, (int)psf_w, taps,
-                       reinterpret_cast<float2 *>(psi_phi));
-    return launch_status("psi_phi_kernel");
+    hipStream_t s = (hipStream_t)stream;
+    const bool lp = lp_dtype != KB_F32;
+    uint32_t *maxabs = lp ? reinterpret_cast<uint32_t *>(lp_scale) : nullptr;
+    const int nsc = (int)(2 * n_img);
+    if (lp) {
+        hipLaunchKernelGGL(lp_zero_kernel, dim3((nsc + 255) / 256), dim3(256), 0, s, maxabs, nsc);
+        kb_status ls = launch_status("lp_zero_kernel");
+        if (ls != KB_OK) return ls;
+    }
+    hipLaunchKernelGGL(psi_phi_kernel, grid, dim3(PP_THREADS), 0, s, img, var, mask, (int)h,
+                       (int)w, (int)psf_h, (int)psf_w, taps, reinterpret_cast<float2 *>(psi_phi),
+                       maxabs);
+    kb_status ls = launch_status("psi_phi_kernel");
+    if (ls != KB_OK || !lp) return ls;
+    hipLaunchKernelGGL(lp_scale_kernel, dim3((nsc + 255) / 256), dim3(256), 0, s, lp_scale, nsc);
+    ls = launch_status("lp_scale_kernel");
+    if (ls != KB_OK) return ls;
+    const size_t npix_img = (size_t)h * (size_t)w;
+    const size_t bx = std::min<size_t>((npix_img + 255) / 256, 2048);
+    hipLaunchKernelGGL(lp_convert_kernel, dim3((unsigned)bx, (unsigned)n_img), dim3(256), 0, s,
+                       reinterpret_cast<const float2 *>(psi_phi), npix_img, lp_scale,
+                       (int)lp_dtype, static_cast<uint32_t *>(psi_phi_lp));
+    return launch_status("lp_convert_kernel");
 }
 
 kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, int64_t n_img,
@@ -608,31 +868,52 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
         return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
     st = check_times_velocities(t, n_img, vel, n_vel);
     if (st != KB_OK) return st;
-    if (dtype != KB_F32) {
-        if (dtype != KB_F16 && dtype != KB_BF16)
-            return fail(KB_EINVAL, "dtype must be KB_F32, KB_F16 or KB_BF16");
-        return fail(KB_EUNSUPPORTED, "16-bit planes are not implemented in this build");
-    }
-    (void)lp_scale;
+    if (dtype != KB_F32 && dtype != KB_F16 && dtype != KB_BF16)
+        return fail(KB_EINVAL, "dtype must be KB_F32, KB_F16 or KB_BF16");
+    if (dtype != KB_F32 && !lp_scale)
+        return fail(KB_EINVAL, "16-bit planes need lp_scale");
     if (!workspace) return fail(KB_EINVAL, "workspace must be non-null");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KB_EINVAL, "workspace must be 256-byte aligned");
-    const size_t ws_need = table_bytes(n_img, n_vel) + order_bytes(n_vel);
+    const size_t ws_need = workspace_layout(n_img, h, w, n_vel).total;
     if (workspace_bytes < ws_need)
         return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need, workspace_bytes);
     hipStream_t s = (hipStream_t)stream;
     st = upload_table(t, n_img, vel, n_vel, h, w, workspace, s);
     if (st != KB_OK) return st;
     const int kc = (int)k_cand;
-    const int32_t *vel_index = reinterpret_cast<const int32_t *>(
-        static_cast<const char *>(workspace) + table_bytes(n_img, n_vel));
+    char *wsb = static_cast<char *>(workspace);
+    const WorkspaceLayout lay = workspace_layout(n_img, h, w, n_vel);
+    SearchLaunch a;
+    StackView &sv = a.sv;
+    sv.planes = planes;
+    sv.inv_scale = reinterpret_cast<const float2 *>(wsb + lay.inv_scale);
+    sv.n_img = (int)n_img;
+    sv.h = (int)h;
+    sv.w = (int)w;
+    sv.disp = reinterpret_cast<const int2 *>(wsb + lay.table);
+    sv.disp_stride = (int)table_stride(n_img);
+    sv.vel_index = reinterpret_cast<const int32_t *>(wsb + lay.order);
+    sv.n_vel = (int)n_vel;
+    sv.k_cand = kc;
+    sv.cand_nu = cand_nu;
+    sv.cand_alpha = cand_alpha;
+    sv.cand_vel = cand_vel;
+    sv.cand_nobs = cand_nobs;
+    a.fmt = dtype;
+    a.stream = s;
+    if (dtype != KB_F32) {
+        const int stride = (int)table_stride(n_img);
+        hipLaunchKernelGGL(inv_scale_kernel, dim3((stride + 63) / 64), dim3(64), 0, s, lp_scale,
+                           (int)n_img, stride, const_cast<float2 *>(sv.inv_scale));
+        st = launch_status("inv_scale_kernel");
+        if (st != KB_OK) return st;
+    }
     const int km = (kc + 1) & ~1;
     switch (km) {
-#define KB_SEARCH_CASE(K)                                                                      \
-    case K:                                                                                    \
-        return launch_search_km<K>(reinterpret_cast<const float2 *>(planes), (int)n_img, (int)h, \
-                                   (int)w, reinterpret_cast<const int2 *>(workspace), vel_index, \
-                                   (int)n_vel, kc, cand_nu, cand_alpha, cand_vel, cand_nobs, s);
+#define KB_SEARCH_CASE(K) \
+    case K:               \
+        return launch_search_km<K>(a);
         KB_SEARCH_KM_LIST(KB_SEARCH_CASE)
 #undef KB_SEARCH_CASE
     }
@@ -654,18 +935,32 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
                     (long long)k_cand);
     if (k_cand > KB_MAX_KCAND)
         return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
-    if (psi_phi_f32 != nullptr)
-        return fail(KB_EUNSUPPORTED, "re-scoring is not implemented in this build");
-    (void)t;
-    (void)vel;
-    (void)n_vel;
-    (void)workspace;
-    (void)workspace_bytes;
     const int64_t npix = h * w;
-    if ((npix + 63) / 64 > 2147483647LL) return fail(KB_EINVAL, "frame too large");
-    const int kc = (int)k_cand;
-    return KB_DISPATCH_KM(kc, launch_topk_km, npix, kc, (int)k, cand_nu, cand_alpha, cand_vel,
-                          cand_nobs, nu, alpha, vel_idx, nobs, (hipStream_t)stream);
+    if ((npix + 3) / 4 > 2147483647LL) return fail(KB_EINVAL, "frame too large");
+    if (psi_phi_f32 != nullptr) {
+        if (n_vel < 1 || n_vel > 65535)
+            return fail(KB_EINVAL, "n_vel must be in [1, 65535] (got %lld)", (long long)n_vel);
+        st = check_times_velocities(t, n_img, vel, n_vel);
+        if (st != KB_OK) return st;
+        if (!workspace) return fail(KB_EINVAL, "re-scoring needs a workspace");
+        if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+            return fail(KB_EINVAL, "workspace must be 256-byte aligned");
+        const size_t ws_need = workspace_layout(n_img, h, w, n_vel).total;
+        if (workspace_bytes < ws_need)
+            return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need,
+                        workspace_bytes);
+        hipStream_t s = (hipStream_t)stream;
+        st = upload_table(t, n_img, vel, n_vel, h, w, workspace, s, false);
+        if (st != KB_OK) return st;
+        return launch_topk_rescore(npix, (int)h, (int)w, (int)n_img,
+                                   reinterpret_cast<const float2 *>(psi_phi_f32),
+                                   reinterpret_cast<const int2 *>(workspace),
+                                   (int)table_stride(n_img), (int)n_vel, (int)k_cand, (int)k,
+                                   cand_vel, nu, alpha, vel_idx, nobs, s);
+    }
+    (void)workspace_bytes;
+    return launch_topk(npix, (int)k_cand, (int)k, cand_nu, cand_alpha, cand_vel, cand_nobs, nu,
+                       alpha, vel_idx, nobs, (hipStream_t)stream);
 }
 
 }  // extern "C"

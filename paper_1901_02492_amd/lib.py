@@ -29,7 +29,7 @@ _SIGNATURES = {
     "kb_displacements": (ctypes.c_int, [_p, _i64, _p, _i64, _p]),
     "kb_make_psi_phi": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _p, _i64, _i64, _p, _i32,
                                        _p, _p, _p]),
-    "kb_search_workspace_bytes": (_sz, [_i64, _i64]),
+    "kb_search_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64]),
     "kb_search": (ctypes.c_int, [_p, _i32, _p, _i64, _i64, _i64, _p, _p, _i64, _i64, _p, _p, _p,
                                  _p, _p, _sz, _p]),
     "kb_topk": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64,
@@ -84,8 +84,8 @@ def displacements(t, vel) -> np.ndarray:
     return out
 
 
-def search_workspace_bytes(n_img: int, n_vel: int) -> int:
-    return int(load().kb_search_workspace_bytes(n_img, n_vel))
+def search_workspace_bytes(n_img: int, h: int, w: int, n_vel: int) -> int:
+    return int(load().kb_search_workspace_bytes(n_img, h, w, n_vel))
 
 
 # ---------------------------------------------------------------------------
@@ -114,21 +114,42 @@ def _dev(t, dtype, name):
     return t.data_ptr()
 
 
-def make_psi_phi(img, var, mask, psf, out=None, stream=None):
+_LP = {"f16": KB_F16, "bf16": KB_BF16}
+
+
+def _lp_torch_dtype(code):
+    torch = _torch()
+    return torch.float16 if code == KB_F16 else torch.bfloat16
+
+
+def make_psi_phi(img, var, mask, psf, out=None, stream=None, lp=None, lp_out=None,
+                 lp_scale=None):
     """psi/phi planes float32 [N][H][W][2] from device img, var (float32) and
-    mask (uint8 or None); psf is a host float32 [ph][pw] array."""
+    mask (uint8 or None); psf is a host float32 [ph][pw] array.
+
+    With lp="f16" or "bf16" also writes the scaled 16-bit copy and returns
+    (planes, lp_planes [N][H][W][2] float16/bfloat16, scale float32 [N][2])."""
     torch = _torch()
     n, h, w = img.shape
     psf = np.ascontiguousarray(np.asarray(psf, dtype=np.float32))
     if out is None:
         out = torch.empty((n, h, w, 2), dtype=torch.float32, device=img.device)
+    code = KB_F32 if lp is None else _LP[lp]
+    lp_ptr = sc_ptr = None
+    if code != KB_F32:
+        if lp_out is None:
+            lp_out = torch.empty((n, h, w, 2), dtype=_lp_torch_dtype(code), device=img.device)
+        if lp_scale is None:
+            lp_scale = torch.empty((n, 2), dtype=torch.float32, device=img.device)
+        lp_ptr = _dev(lp_out, _lp_torch_dtype(code), "psi_phi_lp")
+        sc_ptr = _dev(lp_scale, torch.float32, "lp_scale")
     mp = 0 if mask is None else _dev(mask, torch.uint8, "mask")
     _check(load().kb_make_psi_phi(_dev(img, torch.float32, "img"),
                                   _dev(var, torch.float32, "var"), mp or None, n, h, w,
                                   psf.ctypes.data, psf.shape[0], psf.shape[1],
-                                  _dev(out, torch.float32, "psi_phi"), KB_F32, None, None,
+                                  _dev(out, torch.float32, "psi_phi"), code, lp_ptr, sc_ptr,
                                   _stream(stream)))
-    return out
+    return out if code == KB_F32 else (out, lp_out, lp_scale)
 
 
 def alloc_candidates(h, w, k, device):
@@ -139,26 +160,29 @@ def alloc_candidates(h, w, k, device):
             torch.empty((h, w, k), dtype=torch.int16, device=device))
 
 
-def alloc_workspace(n_img, n_vel, device):
+def alloc_workspace(n_img, h, w, n_vel, device):
     torch = _torch()
-    nb = search_workspace_bytes(n_img, n_vel)
+    nb = search_workspace_bytes(n_img, h, w, n_vel)
     return torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
 
 
-def search(planes, t, vel, k_cand, out=None, workspace=None, stream=None):
-    """kb_search on float32 planes [N][H][W][2]; returns (nu, alpha, vel, nobs)
-    candidate tensors [H][W][k_cand]."""
+def search(planes, t, vel, k_cand, out=None, workspace=None, stream=None, lp_scale=None):
+    """kb_search on planes [N][H][W][2] (float32, or float16 / bfloat16 with
+    their lp_scale); returns (nu, alpha, vel, nobs) candidate tensors
+    [H][W][k_cand], each pixel's candidates in rank order."""
     torch = _torch()
     n, h, w, two = planes.shape
     assert two == 2
+    code = {torch.float32: KB_F32, torch.float16: KB_F16, torch.bfloat16: KB_BF16}[planes.dtype]
+    sc_ptr = None if code == KB_F32 else _dev(lp_scale, torch.float32, "lp_scale")
     t = _host_f64(t)
     vel = _host_f64(vel, 2)
     if out is None:
         out = alloc_candidates(h, w, k_cand, planes.device)
     if workspace is None:
-        workspace = alloc_workspace(n, vel.shape[0], planes.device)
+        workspace = alloc_workspace(n, h, w, vel.shape[0], planes.device)
     cn, ca, cv, co = out
-    _check(load().kb_search(_dev(planes, torch.float32, "planes"), KB_F32, None, n, h, w,
+    _check(load().kb_search(_dev(planes, planes.dtype, "planes"), code, sc_ptr, n, h, w,
                             t.ctypes.data, vel.ctypes.data, vel.shape[0], k_cand,
                             _dev(cn, torch.float32, "cand_nu"),
                             _dev(ca, torch.float32, "cand_alpha"),
@@ -169,28 +193,51 @@ def search(planes, t, vel, k_cand, out=None, workspace=None, stream=None):
     return out
 
 
-def topk(cand, k, n_img, out=None, stream=None):
-    """kb_topk without re-scoring: rank-ordered (nu, alpha, vel, nobs) [H][W][k]."""
+def topk(cand, k, n_img, out=None, stream=None, rescore=None):
+    """kb_topk: rank-ordered (nu, alpha, vel, nobs) [H][W][k].
+
+    rescore=(planes_f32, t, vel, workspace) first recomputes every candidate
+    from the float32 planes (after a 16-bit search)."""
     torch = _torch()
     cn, ca, cv, co = cand
     h, w, kc = cn.shape
     if out is None:
         out = alloc_candidates(h, w, k, cn.device)
     nu, al, vi, no = out
-    _check(load().kb_topk(None, n_img, h, w, None, None, 0,
+    pf = tp = vp = wsp = None
+    nv = wsb = 0
+    if rescore is not None:
+        pf32, t, vel, ws = rescore
+        t = _host_f64(t)
+        vel = _host_f64(vel, 2)
+        if ws is None:
+            ws = alloc_workspace(n_img, h, w, vel.shape[0], cn.device)
+        pf = _dev(pf32, torch.float32, "psi_phi_f32")
+        tp, vp, nv = t.ctypes.data, vel.ctypes.data, vel.shape[0]
+        wsp, wsb = _dev(ws, torch.uint8, "workspace"), ws.numel()
+    _check(load().kb_topk(pf, n_img, h, w, tp, vp, nv,
                           _dev(cn, torch.float32, "cand_nu"), _dev(ca, torch.float32, "cand_alpha"),
                           _dev(cv, torch.int32, "cand_vel"), _dev(co, torch.int16, "cand_nobs"),
                           kc, k, _dev(nu, torch.float32, "nu"), _dev(al, torch.float32, "alpha"),
-                          _dev(vi, torch.int32, "vel"), _dev(no, torch.int16, "nobs"), None, 0,
+                          _dev(vi, torch.int32, "vel"), _dev(no, torch.int16, "nobs"), wsp, wsb,
                           _stream(stream)))
     return out
 
 
-def run_search(img, var, mask, t, psf, vel, k, k_cand=None, stream=None):
+def run_search(img, var, mask, t, psf, vel, k, k_cand=None, stream=None, lp=None):
     """The whole path on device inputs: planes -> search -> top-k.
+    With lp="f16"/"bf16" the search reads the scaled 16-bit planes and top-k
+    re-scores every candidate from the float32 planes.
     Returns (planes, (nu, alpha, vel, nobs))."""
     k_cand = k if k_cand is None else k_cand
-    planes = make_psi_phi(img, var, mask, psf, stream=stream)
-    cand = search(planes, t, vel, k_cand, stream=stream)
-    res = topk(cand, k, img.shape[0], stream=stream)
+    if lp is None:
+        planes = make_psi_phi(img, var, mask, psf, stream=stream)
+        cand = search(planes, t, vel, k_cand, stream=stream)
+        res = topk(cand, k, img.shape[0], stream=stream)
+        return planes, res
+    planes, lp_planes, scale = make_psi_phi(img, var, mask, psf, stream=stream, lp=lp)
+    n, h, w = img.shape
+    ws = alloc_workspace(n, h, w, np.asarray(vel).reshape(-1, 2).shape[0], img.device)
+    cand = search(lp_planes, t, vel, k_cand, stream=stream, lp_scale=scale, workspace=ws)
+    res = topk(cand, k, img.shape[0], stream=stream, rescore=(planes, t, vel, ws))
     return planes, res

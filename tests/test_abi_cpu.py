@@ -95,7 +95,7 @@ def _search_call(**over):
     (dict(kc=65, nv=100, vel=np.zeros((100, 2))), lib.KB_EUNSUPPORTED),
     (dict(t=np.array([0.0, 2.0, 1.0])), lib.KB_EINVAL),
     (dict(dtype=7), lib.KB_EINVAL),
-    (dict(dtype=1), lib.KB_EUNSUPPORTED),
+    (dict(dtype=1), lib.KB_EINVAL),                     # 16-bit planes without scales
     (dict(ws=None), lib.KB_EINVAL),
     (dict(ws=(1 << 20) + 4), lib.KB_EINVAL),            # misaligned workspace
     (dict(wsb=16), lib.KB_ENOMEM),
@@ -104,6 +104,28 @@ def _search_call(**over):
 def test_search_rejects_bad_arguments_before_enqueue(over, status):
     st, msg = _search_call(**over)
     assert st == status and msg
+
+
+def test_make_psi_phi_lp_needs_buffers():
+    L = lib.load()
+    psf = np.ones((3, 3), np.float32)
+    fake = 1 << 20
+    st = L.kb_make_psi_phi(fake, fake, None, 2, 8, 8, psf.ctypes.data, 3, 3, fake, lib.KB_F16,
+                           None, None, None)
+    assert st == lib.KB_EINVAL and "lp" in L.kb_last_error().decode()
+    st = L.kb_make_psi_phi(fake, fake, None, 2, 8, 8, psf.ctypes.data, 3, 3, fake, 9, fake, fake,
+                           None)
+    assert st == lib.KB_EINVAL
+
+
+def test_topk_rescore_checks_times():
+    L = lib.load()
+    fake = 1 << 20
+    t = np.array([0.0, 2.0, 1.0])
+    v = np.zeros((4, 2))
+    st = L.kb_topk(fake, 3, 8, 8, t.ctypes.data, v.ctypes.data, 4, fake, fake, fake, fake, 4, 4,
+                   fake, fake, fake, fake, fake, 1 << 20, None)
+    assert st == lib.KB_EINVAL and "non-decreasing" in L.kb_last_error().decode()
 
 
 def test_make_psi_phi_rejects_bad_psf():
@@ -128,6 +150,8 @@ def test_topk_rejects_k_above_k_cand():
 
 
 def test_workspace_size():
-    assert lib.search_workspace_bytes(15, 600) >= 15 * 600 * 8
-    assert lib.search_workspace_bytes(15, 600) % 256 == 0
-    assert lib.search_workspace_bytes(0, 600) == 0
+    nb = lib.search_workspace_bytes(15, 4096, 4096, 600)
+    assert nb >= 15 * 600 * 8
+    assert nb % 256 == 0
+    assert lib.search_workspace_bytes(0, 8, 8, 600) == 0
+    assert lib.search_workspace_bytes(3, 0, 8, 600) == 0
