@@ -28,6 +28,27 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_TIE_F32 = 8.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1901_02492_amd", "csrc", "kbmi_kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "search_kernel_survey_15x4096x4096_v600_k50.md")
+
+
+def measured_traffic():
+    """HBM bytes per search launch from the committed counter profile, or None
+    if the profile is missing or was taken on a different kernel source."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("kernel_source_sha256:", "traffic_bytes_per_launch:")))
+    if fields.get("kernel_source_sha256", "").strip() != src:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -179,7 +200,7 @@ def main():
                    "step": "kb_make_psi_phi + kb_search + kb_topk"},
         "roofline": {"bound": "hbm", "kernel": "search_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "search_ms": search_ms,
+                     "traffic": measured_traffic(), "search_ms": search_ms,
                      "bytes_per_tie": BYTES_PER_TIE_F32},
         "cpu_baseline": cpu,
     }

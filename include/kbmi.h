@@ -190,6 +190,45 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
                   float *nu, float *alpha, int32_t *vel_idx, int16_t *nobs,
                   void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * Batched search (serving).  One stack of a batch: the kb_search arguments of
+ * that stack.  Every field has kb_search's meaning and rules.
+ */
+typedef struct kb_job {
+    const void *planes;        /* device [n_img][h][w][2] pairs of the batch dtype */
+    const float *lp_scale;     /* device float32 [n_img][2] for 16-bit planes, else NULL */
+    int64_t n_img, h, w;
+    const double *t;           /* host [n_img] */
+    const double *vel;         /* host [n_vel][2] */
+    int64_t n_vel;
+    float *cand_nu;            /* device out [h][w][k_cand] ... */
+    float *cand_alpha;
+    int32_t *cand_vel;
+    int16_t *cand_nobs;
+} kb_job;
+
+/* Device workspace bytes kb_search_batch needs for these jobs (0 if any job
+ * has invalid sizes). */
+size_t kb_search_batch_workspace_bytes(const kb_job *jobs, int64_t n_jobs);
+
+/*
+ * kb_search_batch - kb_search for several stacks in one launch (the serving
+ * path: small stacks share the GPU instead of each under-filling it).  All
+ * jobs share `dtype` and `k_cand`.  Each job's candidates are exactly what
+ * kb_search would write for it alone (same arithmetic, same order), whatever
+ * else is in the batch.
+ *   jobs       host array of n_jobs (1 <= n_jobs <= 4096) descriptors; read
+ *              before return.
+ *   workspace  device, >= kb_search_batch_workspace_bytes(jobs, n_jobs),
+ *              256-byte aligned; overwritten.
+ * The displacement tables and job descriptors are copied host-to-device on
+ * `stream` and the call waits for that copy.
+ * Errors: as kb_search for any job (the message names the job index), plus
+ * KB_EINVAL for n_jobs out of range or more workgroups than one launch holds.
+ */
+kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int64_t k_cand,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ import os
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -38,22 +39,26 @@ def _run(cmd, verbose):
         print(r.stderr, file=sys.stderr)
 
 
-def build_library(verbose: bool = False, out: str = LIB, defines=()) -> str:
+def build_library(verbose: bool = False, out: str = LIB, defines=(), jobs: int = 0) -> str:
     """Compile every source and link libkbmi.so (next to this file unless `out`
-    is given); `defines` are extra -D options.  Returns the library path."""
+    is given); `defines` are extra -D options.  The search kernels are compiled
+    once per plane format, all objects in parallel.  Returns the library path."""
     dflags = [f"-D{d}" for d in defines]
+    jobs = jobs or min(8, os.cpu_count() or 1)
     with tempfile.TemporaryDirectory(prefix="kbmi_build_") as tmp:
-        objs = []
-        host_obj = os.path.join(tmp, "kbmi_host.o")
-        _run(["g++", *HOST_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_host.cpp"), "-o", host_obj],
-             verbose)
-        objs.append(host_obj)
-        dev_obj = os.path.join(tmp, "kbmi_kernels.o")
-        _run([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_kernels.hip"), "-o", dev_obj],
-             verbose)
-        objs.append(dev_obj)
+        steps = [(["g++", *HOST_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_host.cpp"), "-o",
+                   os.path.join(tmp, "kbmi_host.o")], os.path.join(tmp, "kbmi_host.o")),
+                 ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_kernels.hip"),
+                   "-o", os.path.join(tmp, "kbmi_kernels.o")], os.path.join(tmp, "kbmi_kernels.o"))]
+        for fmt in (0, 1, 2):
+            obj = os.path.join(tmp, f"kbmi_search_{fmt}.o")
+            steps.append(([HIPCC, *DEVICE_FLAGS, *dflags, f"-DKBMI_FMT={fmt}", "-c",
+                           os.path.join(CSRC, "kbmi_search.hip"), "-o", obj], obj))
+        with ThreadPoolExecutor(max_workers=jobs) as pool:
+            list(pool.map(lambda st: _run(st[0], verbose), steps))
         tmp_lib = out + ".tmp"
-        _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp_lib, *objs], verbose)
+        _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp_lib,
+              *[o for _, o in steps]], verbose)
         os.replace(tmp_lib, out)
     return out
 

@@ -1,0 +1,423 @@
+// Device-side building blocks of libkbmi shared by its translation units:
+// raw buffer access, candidate keys, the start-pixel tile order, and the
+// trajectory-search kernels (instantiated per plane format by kbmi_search.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kbmi_internal.h"
+
+// Launch-shape defaults (compile-time tunables).
+#ifndef KBMI_STRIP_TILES
+#define KBMI_STRIP_TILES 4      // start-pixel tiles per strip of the tile order
+#endif
+#ifndef KBMI_QUEUE
+#define KBMI_QUEUE 16           // queued candidates per lane before a merge
+#endif
+
+// List lengths compiled for the search: every even length up to KB_MAX_KCAND
+// (each slot costs registers and compare-and-swap work on every insertion).
+#define KB_SEARCH_KM_LIST(X)                                                              \
+    X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) \
+    X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50) X(52) X(54) X(56) X(58)  \
+    X(60) X(62) X(64)
+
+namespace kbmi {
+
+// One search problem as the host launchers see it.
+struct StackView {
+    const void *planes;        // [n_img][h][w] (psi, phi) pairs of the plane format
+    const float2 *inv_scale;   // 16-bit planes: (1/s_psi, 1/s_phi) per image, padded with 0
+    int n_img, h, w;
+    const int2 *disp;          // displacement rows in visiting order, `disp_stride` pairs each
+    int disp_stride;
+    const int32_t *vel_index;  // original index of each visited velocity
+    int n_vel, k_cand;
+    float *cand_nu, *cand_alpha;
+    int32_t *cand_vel;
+    int16_t *cand_nobs;
+};
+
+// One stack of a batched search, as the batch kernel reads it from device memory.
+struct BatchJob {
+    const void *planes;
+    const float2 *inv_scale;
+    const int2 *disp;
+    const int32_t *vel_index;
+    float *cand_nu, *cand_alpha;
+    int32_t *cand_vel;
+    int16_t *cand_nobs;
+    int n_img, h, w, disp_stride, n_vel, nseg, strip, block_begin;
+};
+
+kb_status launch_status(const char *what);
+
+// Search launchers, one translation unit per plane format; km is the (even)
+// compiled list length >= k_cand.
+kb_status launch_search_f32(int km, const StackView &v, hipStream_t s);
+kb_status launch_search_f16(int km, const StackView &v, hipStream_t s);
+kb_status launch_search_bf16(int km, const StackView &v, hipStream_t s);
+kb_status launch_search_batch_f32(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
+                                  int k_cand, hipStream_t s);
+kb_status launch_search_batch_f16(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
+                                  int k_cand, hipStream_t s);
+kb_status launch_search_batch_bf16(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
+                                   int k_cand, hipStream_t s);
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Raw buffer access (stride 0: an access is out of range when its byte offset
+// is >= the buffer's record count, and then a load returns 0).
+// ---------------------------------------------------------------------------
+constexpr int kBufferFlags = 0x00020000;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kBufferFlags);
+}
+
+
+// ---------------------------------------------------------------------------
+// Candidate keys.  A candidate is ordered by (nu descending, j ascending); the
+// 64-bit key (order-preserving bits of nu) << 32 | (0xFFFF - j) << 16 | n_obs
+// compares the same way as unsigned integers.  n_obs never decides an order
+// because j is unique within a pixel.  Key 0 is below every real candidate
+// (nu = -inf maps to 0x007FFFFF) and marks an empty slot.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t nu_order_bits(float nu) {
+    uint32_t u = __float_as_uint(nu);
+    if (u == 0x80000000u) u = 0u;   // -0 ranks equal to +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ inline float nu_from_order_bits(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+__device__ inline uint64_t make_key(float nu, int j, uint32_t nobs) {
+    return ((uint64_t)nu_order_bits(nu) << 32) |
+           (uint64_t)(((uint32_t)(0xFFFF - j) << 16) | (nobs & 0xFFFFu));
+}
+
+// Start-pixel tiles: one wave = 64 adjacent pixels of one row.  Tiles are
+// enumerated in strips `strip` tiles wide (all rows of a strip, then the next
+// strip) so that consecutive workgroups cover a compact 2-D patch, and the
+// workgroup index is remapped so that each of the 8 XCDs (which receive
+// workgroups round-robin) walks one contiguous range of that order and its
+// L2 sees neighbouring patches.
+__device__ inline int xcd_remap(int b, int nblocks) {
+    const int xcd = b & 7, k = b >> 3;
+    const int q = nblocks >> 3, r = nblocks & 7;
+    return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+__device__ inline void strip_tile(int t, int nseg, int h, int strip, int &row, int &seg) {
+    const int fs = nseg / strip;
+    const int full = fs * h * strip;
+    if (t < full) {
+        const int s = t / (h * strip);
+        const int rem = t - s * h * strip;
+        row = rem / strip;
+        seg = s * strip + (rem - (rem / strip) * strip);
+    } else {
+        const int rw = nseg - fs * strip;
+        const int rem = t - full;
+        row = rem / rw;
+        seg = fs * strip + (rem - (rem / rw) * rw);
+    }
+}
+
+struct TileMap {
+    int nseg;     // tiles per row
+    int h;        // rows
+    int strip;    // tiles per strip
+    int nblocks;  // nseg * h
+
+    __device__ inline void map(int b, int &row, int &seg) const {
+        strip_tile(xcd_remap(b, nblocks), nseg, h, strip, row, seg);
+    }
+};
+
+template <int FMT>
+struct PlaneLoad {                       // one (psi, phi) pair as loaded
+    typedef u32x2 type;                  // float32: two words
+};
+template <>
+struct PlaneLoad<KB_F16> {
+    typedef uint32_t type;               // 16-bit: psi low half, phi high half
+};
+template <>
+struct PlaneLoad<KB_BF16> {
+    typedef uint32_t type;
+};
+
+__device__ inline float lp_value(uint32_t bits16, int fmt) {
+    if (fmt == KB_F16) return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+    return __uint_as_float(bits16 << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Trajectory search.
+//
+// One wave (one workgroup) owns 64 adjacent start pixels of one row and walks
+// every velocity in the host-chosen visiting order.  Per velocity each lane
+// gathers its trajectory's N (psi, phi) pairs (one coalesced 512-byte run per
+// image across the wave), sums them in image order and scores nu.
+//
+// Per-pixel selection keeps a descending list of KM >= k_cand keys in
+// registers.  Inserting into it costs a compare-and-swap per slot, and the wave
+// pays for it whenever any lane inserts, so candidates are first filtered
+// against a per-lane threshold (the list's last key at the last merge) and
+// parked in a per-lane LDS queue of PB entries; the queue is merged into the
+// list only when some lane's queue is full (and at the end).  A candidate that
+// fails the threshold can never enter the final list: the threshold only rises.
+//
+// The loads of up to NB images are issued together before they are summed in
+// image order; larger stacks are summed in batches of NB images.  The kernel
+// is bounded to two waves per SIMD: memory-level parallelism comes from the
+// waves, each holding one velocity's NB loads in flight.
+// ---------------------------------------------------------------------------
+template <int KM, int PB>
+constexpr int search_lds_words() {
+    return (3 * PB > KM ? 3 * PB : KM) * 64;
+}
+
+// The search of one tile (start row `row`, start columns seg*64 .. seg*64+63).
+// All scalar arguments are wave-uniform.
+template <int KM, int NB, int PB, int FMT>
+__device__ __forceinline__ void search_tile(
+    uint32_t *lds, const void *__restrict__ planes, const float2 *__restrict__ inv_scale,
+    int n_img, int h, int w, const int2 *__restrict__ disp, int disp_stride,
+    const int32_t *__restrict__ vel_index, int n_vel, int k_cand, int row, int seg,
+    float *__restrict__ cand_nu, float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
+    int16_t *__restrict__ cand_nobs) {
+    uint32_t *q_hi = lds;
+    uint32_t *q_lo = lds + PB * 64;
+    float *q_al = reinterpret_cast<float *>(lds + 2 * PB * 64);
+
+    const int lane = (int)threadIdx.x;
+    const int x0 = seg * 64 + lane;
+    typedef typename PlaneLoad<FMT>::type LoadT;
+    constexpr uint32_t kPix = FMT == KB_F32 ? 8u : 4u;   // bytes per (psi, phi) pair
+    const uint32_t row_bytes = (uint32_t)w * kPix;
+    const size_t img_bytes = (size_t)h * (size_t)w * kPix;
+
+    uint64_t key[KM];
+    float al[KM];
+#pragma unroll
+    for (int s = 0; s < KM; ++s) {
+        key[s] = 0;
+        al[s] = 0.f;
+    }
+    uint64_t thr = 0;   // admission threshold (list tail at the last merge)
+    int nq = 0;         // queued candidates of this lane
+
+    // Issue the loads of images [i0, i0 + NB) of visited velocity jj.  The
+    // table row is fetched whole first (its padding entries lie outside the
+    // frame); rows outside the frame get a zero-length buffer, so their loads
+    // return 0 and add nothing, with no branch.
+    auto issue = [&](int jj, int i0, LoadT(&v)[NB]) {
+        const int4 *t4 = reinterpret_cast<const int4 *>(disp + (size_t)jj * disp_stride + i0);
+        int4 dd[NB / 2];
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) dd[q] = t4[q];
+        // Recomputed per velocity (not hoisted): keeps NB image bases out of
+        // the scalar register file.
+        const char *pbase = reinterpret_cast<const char *>(planes) + (size_t)i0 * img_bytes;
+        asm volatile("" : "+s"(pbase));
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int dx = (b & 1) ? dd[b / 2].z : dd[b / 2].x;
+            const int dy = (b & 1) ? dd[b / 2].w : dd[b / 2].y;
+            const int yy = row + dy;
+            const bool in_rows = (unsigned)yy < (unsigned)h;
+            const char *rb = pbase + (size_t)b * img_bytes +
+                             (size_t)(in_rows ? yy : 0) * (size_t)row_bytes;
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(in_rows ? rb : pbase,
+                                                          in_rows ? row_bytes : 0u);
+            if constexpr (FMT == KB_F32)
+                v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + dx) * (int)kPix, 0, 0);
+            else
+                v[b] = __builtin_amdgcn_raw_buffer_load_b32(rs, (x0 + dx) * (int)kPix, 0, 0);
+        }
+    };
+    // Sum in image order.  Empty slots hold +0, which leaves every sum
+    // unchanged.  16-bit values are decoded and unscaled by an exact power of
+    // two inside the FMA (the product is exact, so the sum rounds once).
+    auto accumulate = [&](int i0, const LoadT(&v)[NB], float &P, float &F) {
+        if constexpr (FMT == KB_F32) {
+            (void)i0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                P += __uint_as_float(v[b].x);
+                F += __uint_as_float(v[b].y);
+            }
+        } else {
+            const float4 *sc4 = reinterpret_cast<const float4 *>(inv_scale + i0);
+            float4 ss[NB / 2];
+#pragma unroll
+            for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float isp = (b & 1) ? ss[b / 2].z : ss[b / 2].x;
+                const float isf = (b & 1) ? ss[b / 2].w : ss[b / 2].y;
+                P = fmaf(lp_value(v[b] & 0xFFFFu, FMT), isp, P);
+                F = fmaf(lp_value(v[b] >> 16, FMT), isf, F);
+            }
+        }
+    };
+    // n_obs: the stored phi is nonzero exactly at valid pixels; empty slots are 0.
+    auto count = [&](const LoadT(&v)[NB]) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if constexpr (FMT == KB_F32) c += v[b].y != 0u;
+            else c += (v[b] >> 16) != 0u;
+        }
+        return c;
+    };
+    auto insert = [&](uint64_t nk, float a) {
+#pragma unroll
+        for (int s = 0; s < KM; ++s) {
+            const bool c = nk > key[s];
+            const uint64_t tk = c ? key[s] : nk;
+            key[s] = c ? nk : key[s];
+            nk = tk;
+            const float ta = c ? al[s] : a;
+            al[s] = c ? a : al[s];
+            a = ta;
+        }
+    };
+    auto merge_queue = [&]() {
+        for (int b = 0; b < PB; ++b) {
+            if (!__any(b < nq)) break;
+            if (b < nq) {
+                const uint64_t nk = ((uint64_t)q_hi[b * 64 + lane] << 32) | q_lo[b * 64 + lane];
+                if (nk > key[KM - 1]) insert(nk, q_al[b * 64 + lane]);
+            }
+        }
+        nq = 0;
+        thr = key[KM - 1];
+    };
+    // Score one trajectory (Sec. 2.1.5: nu = Psi / sqrt(Phi), alpha = Psi / Phi)
+    // and queue it if it beats the admission threshold.  n_obs sits in the
+    // low bits of the key and never decides an order.
+    auto finish = [&](int j, float P, float F, uint32_t c) {
+        const float nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
+        const uint64_t nk = make_key(nu, j, 0u);
+        if (nk > thr) {
+            q_hi[nq * 64 + lane] = (uint32_t)(nk >> 32);
+            q_lo[nq * 64 + lane] = (uint32_t)nk | c;
+            q_al[nq * 64 + lane] = F > 0.f ? P / F : 0.f;
+            ++nq;
+        }
+        if (__any(nq == PB)) merge_queue();
+    };
+
+    if (n_img <= NB) {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = vel_index[jj];   // fetched before the gathers are issued
+            LoadT v[NB];
+            issue(jj, 0, v);
+            float P = 0.f, F = 0.f;
+            accumulate(0, v, P, F);
+            finish(j, P, F, count(v));
+        }
+    } else {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = vel_index[jj];
+            float P = 0.f, F = 0.f;
+            uint32_t c = 0;
+            for (int i0 = 0; i0 < n_img; i0 += NB) {
+                LoadT v[NB];
+                issue(jj, i0, v);
+                accumulate(i0, v, P, F);
+                c += count(v);
+            }
+            finish(j, P, F, c);
+        }
+    }
+    merge_queue();
+
+    // Write the rank-ordered list: stage each field through LDS so that the
+    // wave's stores cover the contiguous [pixels][k_cand] run of its pixels
+    // (one pixel's k_cand <= 64 entries per store instruction).
+    const int npx = (w - seg * 64) < 64 ? (w - seg * 64) : 64;
+    const size_t base = ((size_t)row * (size_t)w + (size_t)seg * 64) * (size_t)k_cand;
+    __syncthreads();
+#pragma unroll
+    for (int field = 0; field < 4; ++field) {
+#pragma unroll
+        for (int s = 0; s < KM; ++s) {
+            const uint32_t hi = (uint32_t)(key[s] >> 32), lo = (uint32_t)key[s];
+            uint32_t v;
+            if (field == 0) v = __float_as_uint(nu_from_order_bits(hi));
+            else if (field == 1) v = __float_as_uint(al[s]);
+            else if (field == 2) v = (uint32_t)(0xFFFF - (int)(lo >> 16));
+            else v = lo & 0xFFFFu;
+            lds[lane * KM + s] = v;
+        }
+        __syncthreads();
+        if (lane < k_cand) {
+            for (int p = 0; p < npx; ++p) {
+                const uint32_t v = lds[p * KM + lane];
+                const size_t o = base + (size_t)p * (size_t)k_cand + (size_t)lane;
+                if (field == 0) cand_nu[o] = __uint_as_float(v);
+                else if (field == 1) cand_alpha[o] = __uint_as_float(v);
+                else if (field == 2) cand_vel[o] = (int32_t)v;
+                else cand_nobs[o] = (int16_t)v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int KM, int NB, int PB, int FMT>
+__global__ __launch_bounds__(64, 2) void search_kernel(
+    const void *__restrict__ planes, const float2 *__restrict__ inv_scale, int n_img, int h,
+    int w, const int2 *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
+    int n_vel, int k_cand, TileMap tiles, float *__restrict__ cand_nu,
+    float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
+    int16_t *__restrict__ cand_nobs) {
+    __shared__ uint32_t lds[search_lds_words<KM, PB>()];
+    int row, seg;
+    tiles.map(blockIdx.x, row, seg);
+    search_tile<KM, NB, PB, FMT>(lds, planes, inv_scale, n_img, h, w, disp, disp_stride,
+                                 vel_index, n_vel, k_cand, row, seg, cand_nu, cand_alpha,
+                                 cand_vel, cand_nobs);
+}
+
+// ---------------------------------------------------------------------------
+// Batched search: one launch covers the tiles of several stacks (the serving
+// path).  Job j owns workgroups [block_begin_j, block_begin_{j+1}) of the
+// XCD-remapped order; each tile runs exactly the single-stack search, so a
+// stack's results do not depend on what it is batched with.
+// ---------------------------------------------------------------------------
+template <int KM, int PB, int FMT>
+__global__ __launch_bounds__(64, 2) void search_batch_kernel(const BatchJob *__restrict__ jobs,
+                                                             int n_jobs, int total_blocks,
+                                                             int k_cand) {
+    __shared__ uint32_t lds[search_lds_words<KM, PB>()];
+    const int t = xcd_remap(blockIdx.x, total_blocks);
+    int lo = 0, hi = n_jobs - 1;   // last job with block_begin <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchJob &jb = jobs[lo];
+    int row, seg;
+    const int h = jb.h;
+    strip_tile(t - jb.block_begin, jb.nseg, h, jb.strip, row, seg);
+    search_tile<KM, 16, PB, FMT>(lds, jb.planes, jb.inv_scale, jb.n_img, h, jb.w, jb.disp,
+                                 jb.disp_stride, jb.vel_index, jb.n_vel, k_cand, row, seg,
+                                 jb.cand_nu, jb.cand_alpha, jb.cand_vel, jb.cand_nobs);
+}
+
+}  // namespace
+}  // namespace kbmi

@@ -130,7 +130,7 @@ size_t order_bytes(int64_t n_vel) {
     return (raw + 255) & ~static_cast<size_t>(255);
 }
 
-int64_t table_stride(int64_t n_img) { return n_img <= 8 ? 8 : (n_img + 15) / 16 * 16; }
+int64_t table_stride(int64_t n_img) { return (n_img + 15) / 16 * 16; }
 
 static size_t align256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
 

@@ -32,10 +32,10 @@ void displacement_table(const double *t, int64_t n_img, const double *vel, int64
 void velocity_order(const double *vel, int64_t n_vel, int32_t *order);
 
 // Device workspace layout: the clamped displacement table in visiting order at
-// offset 0, one row of table_stride(n_img) (dx, dy) pairs per velocity (the
-// rows are padded with entries that lie outside the frame so that the search
-// can fetch a whole row with wide scalar loads), then the original index of
-// each visited velocity (int32 [n_vel]) at table_bytes().
+// offset 0, one row of table_stride(n_img) (dx, dy) pairs per velocity (a
+// multiple of 16; the rows are padded with entries that lie outside the frame
+// so that the search can fetch whole batches of 8 or 16 with wide scalar
+// loads), then the original index of each visited velocity (int32 [n_vel]).
 int64_t table_stride(int64_t n_img);
 size_t table_bytes(int64_t n_img, int64_t n_vel);
 size_t order_bytes(int64_t n_vel);

@@ -19,32 +19,22 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
-#include "kbmi_internal.h"
+#include "kbmi_device.h"
 
-// Launch-shape defaults (compile-time tunables).
-#ifndef KBMI_STRIP_TILES
-#define KBMI_STRIP_TILES 4      // start-pixel tiles per strip of the tile order
-#endif
-#ifndef KBMI_QUEUE
-#define KBMI_QUEUE 16           // queued candidates per lane before a merge
-#endif
 
 namespace kbmi {
-namespace {
 
-// ---------------------------------------------------------------------------
-// Raw buffer access (stride 0: an access is out of range when its byte offset
-// is >= the buffer's record count, and then a load returns 0).
-// ---------------------------------------------------------------------------
-constexpr int kBufferFlags = 0x00020000;
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
-                                             kBufferFlags);
+kb_status launch_status(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(KB_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+    return KB_OK;
 }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Likelihood images.
@@ -217,326 +207,6 @@ __global__ __launch_bounds__(256) void lp_convert_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Candidate keys.  A candidate is ordered by (nu descending, j ascending); the
-// 64-bit key (order-preserving bits of nu) << 32 | (0xFFFF - j) << 16 | n_obs
-// compares the same way as unsigned integers.  n_obs never decides an order
-// because j is unique within a pixel.  Key 0 is below every real candidate
-// (nu = -inf maps to 0x007FFFFF) and marks an empty slot.
-// ---------------------------------------------------------------------------
-__device__ inline uint32_t nu_order_bits(float nu) {
-    uint32_t u = __float_as_uint(nu);
-    if (u == 0x80000000u) u = 0u;   // -0 ranks equal to +0
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ inline float nu_from_order_bits(uint32_t o) {
-    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
-}
-
-__device__ inline uint64_t make_key(float nu, int j, uint32_t nobs) {
-    return ((uint64_t)nu_order_bits(nu) << 32) |
-           (uint64_t)(((uint32_t)(0xFFFF - j) << 16) | (nobs & 0xFFFFu));
-}
-
-// Start-pixel tiles: one wave = 64 adjacent pixels of one row.  Tiles are
-// enumerated in strips `strip` tiles wide (all rows of a strip, then the next
-// strip) so that consecutive workgroups cover a compact 2-D patch, and the
-// workgroup index is remapped so that each of the 8 XCDs (which receive
-// workgroups round-robin) walks one contiguous range of that order and its
-// L2 sees neighbouring patches.
-struct TileMap {
-    int nseg;     // tiles per row
-    int h;        // rows
-    int strip;    // tiles per strip
-    int nblocks;  // nseg * h
-
-    __device__ inline void map(int b, int &row, int &seg) const {
-        const int xcd = b & 7, k = b >> 3;
-        const int q = nblocks >> 3, r = nblocks & 7;
-        const int t = xcd * q + (xcd < r ? xcd : r) + k;
-        const int fs = nseg / strip;
-        const int full = fs * h * strip;
-        if (t < full) {
-            const int s = t / (h * strip);
-            const int rem = t - s * h * strip;
-            row = rem / strip;
-            seg = s * strip + (rem - (rem / strip) * strip);
-        } else {
-            const int rw = nseg - fs * strip;
-            const int rem = t - full;
-            row = rem / rw;
-            seg = fs * strip + (rem - (rem / rw) * rw);
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
-// Trajectory search.
-//
-// One wave (one workgroup) owns 64 adjacent start pixels of one row and walks
-// every velocity in the host-chosen visiting order.  Per velocity each lane
-// gathers its trajectory's N (psi, phi) pairs (one coalesced 512-byte run per
-// image across the wave), sums them in image order and scores nu.
-//
-// Per-pixel selection keeps a descending list of KM >= k_cand keys in
-// registers.  Inserting into it costs a compare-and-swap per slot, and the wave
-// pays for it whenever any lane inserts, so candidates are first filtered
-// against a per-lane threshold (the list's last key at the last merge) and
-// parked in a per-lane LDS queue of PB entries; the queue is merged into the
-// list only when some lane's queue is full (and at the end).  A candidate that
-// fails the threshold can never enter the final list: the threshold only rises.
-//
-// The loads of up to NB images are issued together before they are summed in
-// image order; larger stacks are summed in batches of NB images.  The kernel
-// is bounded to two waves per SIMD: memory-level parallelism comes from the
-// waves, each holding one velocity's NB loads in flight.
-// ---------------------------------------------------------------------------
-template <int FMT>
-struct PlaneLoad {                       // one (psi, phi) pair as loaded
-    typedef u32x2 type;                  // float32: two words
-};
-template <>
-struct PlaneLoad<KB_F16> {
-    typedef uint32_t type;               // 16-bit: psi low half, phi high half
-};
-template <>
-struct PlaneLoad<KB_BF16> {
-    typedef uint32_t type;
-};
-
-__device__ inline float lp_value(uint32_t bits16, int fmt) {
-    if (fmt == KB_F16) return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
-    return __uint_as_float(bits16 << 16);
-}
-
-// One search problem as the host launchers see it.
-struct StackView {
-    const void *planes;        // [n_img][h][w] (psi, phi) pairs of format FMT
-    const float2 *inv_scale;   // 16-bit planes: (1/s_psi, 1/s_phi) per image, padded with 0
-    int n_img, h, w;
-    const int2 *disp;          // displacement rows in visiting order, `disp_stride` pairs each
-    int disp_stride;
-    const int32_t *vel_index;  // original index of each visited velocity
-    int n_vel, k_cand;
-    float *cand_nu, *cand_alpha;
-    int32_t *cand_vel;
-    int16_t *cand_nobs;
-};
-
-// ---------------------------------------------------------------------------
-// Trajectory search.
-//
-// One wave (one workgroup) owns 64 adjacent start pixels of one row and walks
-// every velocity in the host-chosen visiting order.  Per velocity each lane
-// gathers its trajectory's N (psi, phi) pairs (one coalesced 512-byte run per
-// image across the wave), sums them in image order and scores nu.
-//
-// Per-pixel selection keeps a descending list of KM >= k_cand keys in
-// registers.  Inserting into it costs a compare-and-swap per slot, and the wave
-// pays for it whenever any lane inserts, so candidates are first filtered
-// against a per-lane threshold (the list's last key at the last merge) and
-// parked in a per-lane LDS queue of PB entries; the queue is merged into the
-// list only when some lane's queue is full (and at the end).  A candidate that
-// fails the threshold can never enter the final list: the threshold only rises.
-//
-// The loads of up to NB images are issued together before they are summed in
-// image order; larger stacks are summed in batches of NB images.  The kernel
-// is bounded to two waves per SIMD: memory-level parallelism comes from the
-// waves, each holding one velocity's NB loads in flight.
-// ---------------------------------------------------------------------------
-template <int KM, int NB, int PB, int FMT>
-__global__ __launch_bounds__(64, 2) void search_kernel(
-    const void *__restrict__ planes, const float2 *__restrict__ inv_scale, int n_img, int h,
-    int w, const int2 *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
-    int n_vel, int k_cand, TileMap tiles, float *__restrict__ cand_nu,
-    float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
-    int16_t *__restrict__ cand_nobs) {
-    constexpr int kLdsWords = (3 * PB > KM ? 3 * PB : KM) * 64;
-    __shared__ uint32_t lds[kLdsWords];
-    uint32_t *q_hi = lds;
-    uint32_t *q_lo = lds + PB * 64;
-    float *q_al = reinterpret_cast<float *>(lds + 2 * PB * 64);
-
-    const int lane = (int)threadIdx.x;
-    int row, seg;
-    tiles.map(blockIdx.x, row, seg);
-    const int x0 = seg * 64 + lane;
-    typedef typename PlaneLoad<FMT>::type LoadT;
-    constexpr uint32_t kPix = FMT == KB_F32 ? 8u : 4u;   // bytes per (psi, phi) pair
-    const uint32_t row_bytes = (uint32_t)w * kPix;
-    const size_t img_bytes = (size_t)h * (size_t)w * kPix;
-
-    uint64_t key[KM];
-    float al[KM];
-#pragma unroll
-    for (int s = 0; s < KM; ++s) {
-        key[s] = 0;
-        al[s] = 0.f;
-    }
-    uint64_t thr = 0;   // admission threshold (list tail at the last merge)
-    int nq = 0;         // queued candidates of this lane
-
-    // Issue the loads of images [i0, i0 + NB) of visited velocity jj.  The
-    // table row is fetched whole first (its padding entries lie outside the
-    // frame); rows outside the frame get a zero-length buffer, so their loads
-    // return 0 and add nothing, with no branch.
-    auto issue = [&](int jj, int i0, LoadT(&v)[NB]) {
-        const int4 *t4 = reinterpret_cast<const int4 *>(disp + (size_t)jj * disp_stride + i0);
-        int4 dd[NB / 2];
-#pragma unroll
-        for (int q = 0; q < NB / 2; ++q) dd[q] = t4[q];
-        // Recomputed per velocity (not hoisted): keeps NB image bases out of
-        // the scalar register file.
-        const char *pbase = reinterpret_cast<const char *>(planes) + (size_t)i0 * img_bytes;
-        asm volatile("" : "+s"(pbase));
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int dx = (b & 1) ? dd[b / 2].z : dd[b / 2].x;
-            const int dy = (b & 1) ? dd[b / 2].w : dd[b / 2].y;
-            const int yy = row + dy;
-            const bool in_rows = (unsigned)yy < (unsigned)h;
-            const char *rb = pbase + (size_t)b * img_bytes +
-                             (size_t)(in_rows ? yy : 0) * (size_t)row_bytes;
-            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(in_rows ? rb : pbase,
-                                                          in_rows ? row_bytes : 0u);
-            if constexpr (FMT == KB_F32)
-                v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + dx) * (int)kPix, 0, 0);
-            else
-                v[b] = __builtin_amdgcn_raw_buffer_load_b32(rs, (x0 + dx) * (int)kPix, 0, 0);
-        }
-    };
-    // Sum in image order.  Empty slots hold +0, which leaves every sum
-    // unchanged.  16-bit values are decoded and unscaled by an exact power of
-    // two inside the FMA (the product is exact, so the sum rounds once).
-    auto accumulate = [&](int i0, const LoadT(&v)[NB], float &P, float &F) {
-        if constexpr (FMT == KB_F32) {
-            (void)i0;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                P += __uint_as_float(v[b].x);
-                F += __uint_as_float(v[b].y);
-            }
-        } else {
-            const float4 *sc4 = reinterpret_cast<const float4 *>(inv_scale + i0);
-            float4 ss[NB / 2];
-#pragma unroll
-            for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const float isp = (b & 1) ? ss[b / 2].z : ss[b / 2].x;
-                const float isf = (b & 1) ? ss[b / 2].w : ss[b / 2].y;
-                P = fmaf(lp_value(v[b] & 0xFFFFu, FMT), isp, P);
-                F = fmaf(lp_value(v[b] >> 16, FMT), isf, F);
-            }
-        }
-    };
-    // n_obs: the stored phi is nonzero exactly at valid pixels; empty slots are 0.
-    auto count = [&](const LoadT(&v)[NB]) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if constexpr (FMT == KB_F32) c += v[b].y != 0u;
-            else c += (v[b] >> 16) != 0u;
-        }
-        return c;
-    };
-    auto insert = [&](uint64_t nk, float a) {
-#pragma unroll
-        for (int s = 0; s < KM; ++s) {
-            const bool c = nk > key[s];
-            const uint64_t tk = c ? key[s] : nk;
-            key[s] = c ? nk : key[s];
-            nk = tk;
-            const float ta = c ? al[s] : a;
-            al[s] = c ? a : al[s];
-            a = ta;
-        }
-    };
-    auto merge_queue = [&]() {
-        for (int b = 0; b < PB; ++b) {
-            if (!__any(b < nq)) break;
-            if (b < nq) {
-                const uint64_t nk = ((uint64_t)q_hi[b * 64 + lane] << 32) | q_lo[b * 64 + lane];
-                if (nk > key[KM - 1]) insert(nk, q_al[b * 64 + lane]);
-            }
-        }
-        nq = 0;
-        thr = key[KM - 1];
-    };
-    // Score one trajectory (Sec. 2.1.5: nu = Psi / sqrt(Phi), alpha = Psi / Phi)
-    // and queue it if it beats the admission threshold.  n_obs sits in the
-    // low bits of the key and never decides an order.
-    auto finish = [&](int j, float P, float F, uint32_t c) {
-        const float nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
-        const uint64_t nk = make_key(nu, j, 0u);
-        if (nk > thr) {
-            q_hi[nq * 64 + lane] = (uint32_t)(nk >> 32);
-            q_lo[nq * 64 + lane] = (uint32_t)nk | c;
-            q_al[nq * 64 + lane] = F > 0.f ? P / F : 0.f;
-            ++nq;
-        }
-        if (__any(nq == PB)) merge_queue();
-    };
-
-    if (n_img <= NB) {
-        for (int jj = 0; jj < n_vel; ++jj) {
-            const int j = vel_index[jj];   // fetched before the gathers are issued
-            LoadT v[NB];
-            issue(jj, 0, v);
-            float P = 0.f, F = 0.f;
-            accumulate(0, v, P, F);
-            finish(j, P, F, count(v));
-        }
-    } else {
-        for (int jj = 0; jj < n_vel; ++jj) {
-            const int j = vel_index[jj];
-            float P = 0.f, F = 0.f;
-            uint32_t c = 0;
-            for (int i0 = 0; i0 < n_img; i0 += NB) {
-                LoadT v[NB];
-                issue(jj, i0, v);
-                accumulate(i0, v, P, F);
-                c += count(v);
-            }
-            finish(j, P, F, c);
-        }
-    }
-    merge_queue();
-
-    // Write the rank-ordered list: stage each field through LDS so that the
-    // wave's stores cover the contiguous [pixels][k_cand] run of its pixels
-    // (one pixel's k_cand <= 64 entries per store instruction).
-    const int npx = (w - seg * 64) < 64 ? (w - seg * 64) : 64;
-    const size_t base = ((size_t)row * (size_t)w + (size_t)seg * 64) * (size_t)k_cand;
-    __syncthreads();
-#pragma unroll
-    for (int field = 0; field < 4; ++field) {
-#pragma unroll
-        for (int s = 0; s < KM; ++s) {
-            const uint32_t hi = (uint32_t)(key[s] >> 32), lo = (uint32_t)key[s];
-            uint32_t v;
-            if (field == 0) v = __float_as_uint(nu_from_order_bits(hi));
-            else if (field == 1) v = __float_as_uint(al[s]);
-            else if (field == 2) v = (uint32_t)(0xFFFF - (int)(lo >> 16));
-            else v = lo & 0xFFFFu;
-            lds[lane * KM + s] = v;
-        }
-        __syncthreads();
-        if (lane < k_cand) {
-            for (int p = 0; p < npx; ++p) {
-                const uint32_t v = lds[p * KM + lane];
-                const size_t o = base + (size_t)p * (size_t)k_cand + (size_t)lane;
-                if (field == 0) cand_nu[o] = __uint_as_float(v);
-                else if (field == 1) cand_alpha[o] = __uint_as_float(v);
-                else if (field == 2) cand_vel[o] = (int32_t)v;
-                else cand_nobs[o] = (int16_t)v;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Final selection.  One thread per candidate: a 256-thread block holds whole
 // pixels (256 / k_cand of them), reads their candidate runs with coalesced
 // loads, and each thread checks that its candidate precedes the next one of
@@ -655,53 +325,6 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
 // ---------------------------------------------------------------------------
 // Host-side launch helpers.
 // ---------------------------------------------------------------------------
-kb_status launch_status(const char *what) {
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return fail(KB_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
-    return KB_OK;
-}
-
-struct SearchLaunch {
-    StackView sv;
-    int fmt;
-    hipStream_t stream;
-};
-
-TileMap tile_map(int w, int h) {
-    TileMap tm;
-    tm.nseg = (w + 63) / 64;
-    tm.h = h;
-    tm.strip = tm.nseg < KBMI_STRIP_TILES ? tm.nseg : KBMI_STRIP_TILES;
-    tm.nblocks = tm.nseg * h;
-    return tm;
-}
-
-template <int KM, int NB, int FMT>
-kb_status launch_search_fmt(const SearchLaunch &a) {
-    constexpr int PB = KBMI_QUEUE;
-    const StackView &v = a.sv;
-    const TileMap tm = tile_map(v.w, v.h);
-    hipLaunchKernelGGL((search_kernel<KM, NB, PB, FMT>), dim3(tm.nblocks), dim3(64), 0, a.stream,
-                       v.planes, v.inv_scale, v.n_img, v.h, v.w, v.disp, v.disp_stride,
-                       v.vel_index, v.n_vel, v.k_cand, tm, v.cand_nu, v.cand_alpha, v.cand_vel,
-                       v.cand_nobs);
-    return launch_status("search_kernel");
-}
-
-template <int KM, int NB>
-kb_status launch_search_nb(const SearchLaunch &a) {
-    static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
-    if (a.fmt == KB_F16) return launch_search_fmt<KM, NB, KB_F16>(a);
-    if (a.fmt == KB_BF16) return launch_search_fmt<KM, NB, KB_BF16>(a);
-    return launch_search_fmt<KM, NB, KB_F32>(a);
-}
-
-template <int KM>
-kb_status launch_search_km(const SearchLaunch &a) {
-    if (a.sv.n_img <= 8) return launch_search_nb<KM, 8>(a);
-    return launch_search_nb<KM, 16>(a);
-}
 
 // 1/s per image and plane for the 16-bit search, padded with 0 to the table
 // stride (padding images then contribute exactly 0).
@@ -734,13 +357,6 @@ kb_status launch_topk(int64_t npix, int k_cand, int k, const float *cn, const fl
                        k_cand, k, cn, ca, cv, co, nu, al, vi, no);
     return launch_status("topk_kernel");
 }
-
-// List lengths compiled for the search: every even length up to KB_MAX_KCAND
-// (each slot costs registers and compare-and-swap work on every insertion).
-#define KB_SEARCH_KM_LIST(X)                                                              \
-    X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) \
-    X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50) X(52) X(54) X(56) X(58)  \
-    X(60) X(62) X(64)
 
 kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
     if (n_img < 1 || n_img > 32767)
@@ -884,8 +500,7 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     const int kc = (int)k_cand;
     char *wsb = static_cast<char *>(workspace);
     const WorkspaceLayout lay = workspace_layout(n_img, h, w, n_vel);
-    SearchLaunch a;
-    StackView &sv = a.sv;
+    StackView sv;
     sv.planes = planes;
     sv.inv_scale = reinterpret_cast<const float2 *>(wsb + lay.inv_scale);
     sv.n_img = (int)n_img;
@@ -900,8 +515,6 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     sv.cand_alpha = cand_alpha;
     sv.cand_vel = cand_vel;
     sv.cand_nobs = cand_nobs;
-    a.fmt = dtype;
-    a.stream = s;
     if (dtype != KB_F32) {
         const int stride = (int)table_stride(n_img);
         hipLaunchKernelGGL(inv_scale_kernel, dim3((stride + 63) / 64), dim3(64), 0, s, lp_scale,
@@ -910,14 +523,9 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
         if (st != KB_OK) return st;
     }
     const int km = (kc + 1) & ~1;
-    switch (km) {
-#define KB_SEARCH_CASE(K) \
-    case K:               \
-        return launch_search_km<K>(a);
-        KB_SEARCH_KM_LIST(KB_SEARCH_CASE)
-#undef KB_SEARCH_CASE
-    }
-    return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
+    if (dtype == KB_F16) return launch_search_f16(km, sv, s);
+    if (dtype == KB_BF16) return launch_search_bf16(km, sv, s);
+    return launch_search_f32(km, sv, s);
 }
 
 kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
@@ -961,6 +569,154 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
     (void)workspace_bytes;
     return launch_topk(npix, (int)k_cand, (int)k, cand_nu, cand_alpha, cand_vel, cand_nobs, nu,
                        alpha, vel_idx, nobs, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Batch workspace: the device job descriptors, then per job its table, visiting
+// order and 16-bit inverse scales (each 256-byte aligned).
+struct BatchLayout {
+    std::vector<size_t> table, order, inv_scale;
+    size_t total;
+};
+
+size_t round256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
+
+bool batch_layout(const kb_job *jobs, int64_t n_jobs, BatchLayout &l) {
+    if (!jobs || n_jobs < 1 || n_jobs > 4096) return false;
+    size_t off = round256(sizeof(BatchJob) * static_cast<size_t>(n_jobs));
+    l.table.resize(n_jobs);
+    l.order.resize(n_jobs);
+    l.inv_scale.resize(n_jobs);
+    for (int64_t q = 0; q < n_jobs; ++q) {
+        const kb_job &j = jobs[q];
+        if (j.n_img < 1 || j.n_vel < 1 || j.h < 1 || j.w < 1) return false;
+        l.table[q] = off;
+        off += table_bytes(j.n_img, j.n_vel);
+        l.order[q] = off;
+        off += order_bytes(j.n_vel);
+        l.inv_scale[q] = off;
+        off += round256(static_cast<size_t>(table_stride(j.n_img)) * 8);
+    }
+    l.total = off;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kb_search_batch_workspace_bytes(const kb_job *jobs, int64_t n_jobs) {
+    BatchLayout l;
+    return batch_layout(jobs, n_jobs, l) ? l.total : 0;
+}
+
+kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int64_t k_cand,
+                          void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!jobs || n_jobs < 1 || n_jobs > 4096)
+        return fail(KB_EINVAL, "n_jobs must be in [1, 4096] (got %lld)", (long long)n_jobs);
+    if (dtype != KB_F32 && dtype != KB_F16 && dtype != KB_BF16)
+        return fail(KB_EINVAL, "dtype must be KB_F32, KB_F16 or KB_BF16");
+    if (k_cand < 1) return fail(KB_EINVAL, "k_cand must be >= 1");
+    if (k_cand > KB_MAX_KCAND)
+        return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
+    int64_t total_blocks = 0;
+    for (int64_t q = 0; q < n_jobs; ++q) {
+        const kb_job &j = jobs[q];
+        if (!j.planes || !j.cand_nu || !j.cand_alpha || !j.cand_vel || !j.cand_nobs)
+            return fail(KB_EINVAL, "job %lld: planes and candidate outputs must be non-null",
+                        (long long)q);
+        kb_status st = check_frame(j.n_img, j.h, j.w);
+        if (st != KB_OK) return fail(st, "job %lld: %s", (long long)q, kb_last_error());
+        if (j.n_vel < 1 || j.n_vel > 65535)
+            return fail(KB_EINVAL, "job %lld: n_vel must be in [1, 65535]", (long long)q);
+        if (k_cand > j.n_vel)
+            return fail(KB_EINVAL, "job %lld: k_cand exceeds n_vel", (long long)q);
+        st = check_times_velocities(j.t, j.n_img, j.vel, j.n_vel);
+        if (st != KB_OK) return fail(st, "job %lld: %s", (long long)q, kb_last_error());
+        if (dtype != KB_F32 && !j.lp_scale)
+            return fail(KB_EINVAL, "job %lld: 16-bit planes need lp_scale", (long long)q);
+        total_blocks += (j.w + 63) / 64 * j.h;
+    }
+    if (total_blocks > 2147483647LL)
+        return fail(KB_EINVAL, "batch holds more workgroups than one launch");
+    BatchLayout lay;
+    batch_layout(jobs, n_jobs, lay);
+    if (!workspace) return fail(KB_EINVAL, "workspace must be non-null");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(KB_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < lay.total)
+        return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", lay.total, workspace_bytes);
+
+    // Stage descriptors and tables on the host, then one copy.
+    char *ws = static_cast<char *>(workspace);
+    std::vector<char> host(lay.total, 0);
+    BatchJob *desc = reinterpret_cast<BatchJob *>(host.data());
+    int block_begin = 0;
+    for (int64_t q = 0; q < n_jobs; ++q) {
+        const kb_job &j = jobs[q];
+        std::vector<int32_t> order(static_cast<size_t>(j.n_vel));
+        velocity_order(j.vel, j.n_vel, order.data());
+        std::vector<double> vel_visit(static_cast<size_t>(j.n_vel) * 2);
+        for (int64_t v = 0; v < j.n_vel; ++v) {
+            vel_visit[2 * v] = j.vel[2 * order[v]];
+            vel_visit[2 * v + 1] = j.vel[2 * order[v] + 1];
+        }
+        std::vector<int32_t> dense(static_cast<size_t>(j.n_img) * j.n_vel * 2);
+        displacement_table(j.t, j.n_img, vel_visit.data(), j.n_vel, dense.data(), j.w, j.h);
+        const int64_t stride = table_stride(j.n_img);
+        int32_t *table = reinterpret_cast<int32_t *>(host.data() + lay.table[q]);
+        for (int64_t v = 0; v < j.n_vel; ++v)
+            for (int64_t i = 0; i < stride; ++i) {
+                const bool real = i < j.n_img;
+                table[(v * stride + i) * 2] = real ? dense[(v * j.n_img + i) * 2] : 0;
+                table[(v * stride + i) * 2 + 1] =
+                    real ? dense[(v * j.n_img + i) * 2 + 1] : (int32_t)j.h;
+            }
+        std::memcpy(host.data() + lay.order[q], order.data(), order.size() * sizeof(int32_t));
+        BatchJob &d = desc[q];
+        d.planes = j.planes;
+        d.inv_scale = reinterpret_cast<const float2 *>(ws + lay.inv_scale[q]);
+        d.disp = reinterpret_cast<const int2 *>(ws + lay.table[q]);
+        d.vel_index = reinterpret_cast<const int32_t *>(ws + lay.order[q]);
+        d.cand_nu = j.cand_nu;
+        d.cand_alpha = j.cand_alpha;
+        d.cand_vel = j.cand_vel;
+        d.cand_nobs = j.cand_nobs;
+        d.n_img = (int)j.n_img;
+        d.h = (int)j.h;
+        d.w = (int)j.w;
+        d.disp_stride = (int)stride;
+        d.n_vel = (int)j.n_vel;
+        d.nseg = (int)((j.w + 63) / 64);
+        d.strip = d.nseg < KBMI_STRIP_TILES ? d.nseg : KBMI_STRIP_TILES;
+        d.block_begin = block_begin;
+        block_begin += d.nseg * d.h;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(KB_EDEVICE, "batch upload failed: %s", hipGetErrorString(e));
+    if (dtype != KB_F32) {
+        for (int64_t q = 0; q < n_jobs; ++q) {
+            const int stride = (int)table_stride(jobs[q].n_img);
+            hipLaunchKernelGGL(inv_scale_kernel, dim3((stride + 63) / 64), dim3(64), 0, s,
+                               jobs[q].lp_scale, (int)jobs[q].n_img, stride,
+                               reinterpret_cast<float2 *>(ws + lay.inv_scale[q]));
+            kb_status st = launch_status("inv_scale_kernel");
+            if (st != KB_OK) return st;
+        }
+    }
+    const int kc = (int)k_cand;
+    const int km = (kc + 1) & ~1;
+    const BatchJob *dj = reinterpret_cast<const BatchJob *>(ws);
+    if (dtype == KB_F16) return launch_search_batch_f16(km, dj, (int)n_jobs, (int)total_blocks, kc, s);
+    if (dtype == KB_BF16) return launch_search_batch_bf16(km, dj, (int)n_jobs, (int)total_blocks, kc, s);
+    return launch_search_batch_f32(km, dj, (int)n_jobs, (int)total_blocks, kc, s);
 }
 
 }  // extern "C"

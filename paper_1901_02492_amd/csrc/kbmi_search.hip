@@ -1,0 +1,83 @@
+// Trajectory-search launchers for one plane format (KBMI_FMT: 0 = float32,
+// 1 = IEEE half, 2 = bfloat16); the build compiles this file once per format.
+#include "kbmi_device.h"
+
+#ifndef KBMI_FMT
+#error "compile with -DKBMI_FMT=0|1|2"
+#endif
+
+#if KBMI_FMT == 0
+#define KBMI_LAUNCH launch_search_f32
+#define KBMI_LAUNCH_BATCH launch_search_batch_f32
+#elif KBMI_FMT == 1
+#define KBMI_LAUNCH launch_search_f16
+#define KBMI_LAUNCH_BATCH launch_search_batch_f16
+#else
+#define KBMI_LAUNCH launch_search_bf16
+#define KBMI_LAUNCH_BATCH launch_search_batch_bf16
+#endif
+
+namespace kbmi {
+namespace {
+
+TileMap tile_map(int w, int h) {
+    TileMap tm;
+    tm.nseg = (w + 63) / 64;
+    tm.h = h;
+    tm.strip = tm.nseg < KBMI_STRIP_TILES ? tm.nseg : KBMI_STRIP_TILES;
+    tm.nblocks = tm.nseg * h;
+    return tm;
+}
+
+template <int KM, int NB>
+kb_status launch_one(const StackView &v, hipStream_t s) {
+    constexpr int PB = KBMI_QUEUE;
+    static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
+    const TileMap tm = tile_map(v.w, v.h);
+    hipLaunchKernelGGL((search_kernel<KM, NB, PB, KBMI_FMT>), dim3(tm.nblocks), dim3(64), 0, s,
+                       v.planes, v.inv_scale, v.n_img, v.h, v.w, v.disp, v.disp_stride,
+                       v.vel_index, v.n_vel, v.k_cand, tm, v.cand_nu, v.cand_alpha, v.cand_vel,
+                       v.cand_nobs);
+    return launch_status("search_kernel");
+}
+
+template <int KM>
+kb_status launch_km(const StackView &v, hipStream_t s) {
+    return v.n_img <= 8 ? launch_one<KM, 8>(v, s) : launch_one<KM, 16>(v, s);
+}
+
+template <int KM>
+kb_status launch_batch_km(const BatchJob *jobs, int n_jobs, int total_blocks, int k_cand,
+                          hipStream_t s) {
+    constexpr int PB = KBMI_QUEUE;
+    hipLaunchKernelGGL((search_batch_kernel<KM, PB, KBMI_FMT>), dim3(total_blocks), dim3(64), 0, s,
+                       jobs, n_jobs, total_blocks, k_cand);
+    return launch_status("search_batch_kernel");
+}
+
+}  // namespace
+
+kb_status KBMI_LAUNCH(int km, const StackView &v, hipStream_t s) {
+    switch (km) {
+#define KB_CASE(K) \
+    case K:        \
+        return launch_km<K>(v, s);
+        KB_SEARCH_KM_LIST(KB_CASE)
+#undef KB_CASE
+    }
+    return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
+}
+
+kb_status KBMI_LAUNCH_BATCH(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
+                            int k_cand, hipStream_t s) {
+    switch (km) {
+#define KB_CASE(K) \
+    case K:        \
+        return launch_batch_km<K>(jobs, n_jobs, total_blocks, k_cand, s);
+        KB_SEARCH_KM_LIST(KB_CASE)
+#undef KB_CASE
+    }
+    return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
+}
+
+}  // namespace kbmi

@@ -34,7 +34,16 @@ _SIGNATURES = {
                                  _p, _p, _sz, _p]),
     "kb_topk": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64,
                                _p, _p, _p, _p, _p, _sz, _p]),
+    "kb_search_batch_workspace_bytes": (_sz, [_p, _i64]),
+    "kb_search_batch": (ctypes.c_int, [_p, _i64, _i32, _i64, _p, _sz, _p]),
 }
+
+
+class KbJob(ctypes.Structure):
+    """Mirror of the C struct kb_job (one stack of a batched search)."""
+    _fields_ = [("planes", _p), ("lp_scale", _p), ("n_img", _i64), ("h", _i64), ("w", _i64),
+                ("t", _p), ("vel", _p), ("n_vel", _i64), ("cand_nu", _p), ("cand_alpha", _p),
+                ("cand_vel", _p), ("cand_nobs", _p)]
 
 
 class KbError(RuntimeError):
@@ -222,6 +231,51 @@ def topk(cand, k, n_img, out=None, stream=None, rescore=None):
                           _dev(vi, torch.int32, "vel"), _dev(no, torch.int16, "nobs"), wsp, wsb,
                           _stream(stream)))
     return out
+
+
+def _job_array(jobs):
+    """jobs: list of dicts with planes, t, vel, out (4 tensors) and optional lp_scale."""
+    torch = _torch()
+    arr = (KbJob * len(jobs))()
+    keep = []
+    for q, jb in enumerate(jobs):
+        planes = jb["planes"]
+        n, h, w, _ = planes.shape
+        t = _host_f64(jb["t"])
+        vel = _host_f64(jb["vel"], 2)
+        keep += [t, vel]
+        cn, ca, cv, co = jb["out"]
+        sc = jb.get("lp_scale")
+        arr[q] = KbJob(_dev(planes, planes.dtype, "planes"),
+                       None if sc is None else _dev(sc, torch.float32, "lp_scale"),
+                       n, h, w, t.ctypes.data, vel.ctypes.data, vel.shape[0],
+                       _dev(cn, torch.float32, "cand_nu"), _dev(ca, torch.float32, "cand_alpha"),
+                       _dev(cv, torch.int32, "cand_vel"), _dev(co, torch.int16, "cand_nobs"))
+    return arr, keep
+
+
+def search_batch_workspace_bytes(jobs) -> int:
+    arr, keep = _job_array(jobs)
+    return int(load().kb_search_batch_workspace_bytes(ctypes.addressof(arr), len(jobs)))
+
+
+def search_batch(jobs, k_cand, workspace=None, stream=None):
+    """kb_search_batch over several stacks sharing one plane dtype and k_cand.
+
+    jobs: list of dicts(planes=[N][H][W][2] tensor, t, vel, out=(nu, alpha, vel, nobs)
+    tensors [H][W][k_cand], lp_scale=None or [N][2]).  Returns the workspace."""
+    torch = _torch()
+    code = {torch.float32: KB_F32, torch.float16: KB_F16,
+            torch.bfloat16: KB_BF16}[jobs[0]["planes"].dtype]
+    arr, keep = _job_array(jobs)
+    L = load()
+    nb = int(L.kb_search_batch_workspace_bytes(ctypes.addressof(arr), len(jobs)))
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=jobs[0]["planes"].device)
+    _check(L.kb_search_batch(ctypes.addressof(arr), len(jobs), code, k_cand,
+                             _dev(workspace, torch.uint8, "workspace"), workspace.numel(),
+                             _stream(stream)))
+    return workspace
 
 
 def run_search(img, var, mask, t, psf, vel, k, k_cand=None, stream=None, lp=None):

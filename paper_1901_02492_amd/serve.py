@@ -1,0 +1,290 @@
+"""Continuous-batching search server.
+
+Requests (image stacks of uneven image count, frame size and velocity grid)
+arrive while others run.  The scheduler
+
+  * admits requests in arrival order while their device footprint fits the
+    HBM budget (a request larger than the whole budget fails at once);
+  * prepares each admitted request on the device (inputs, likelihood planes,
+    candidate and result buffers) as soon as it is admitted;
+  * launches the searches of everything prepared since the last launch as ONE
+    batched search (kb_search_batch: one persistent launch over the tiles of
+    all those stacks) followed by each stack's final top-k, keeping up to
+    `max_inflight` such batches queued on the device so it never idles
+    between them;
+  * resolves each request's future when its results are ready and frees its
+    memory, which admits the next requests.
+
+A request's result is the same as running it alone (the batched search runs
+the single-stack arithmetic per tile).  All device work sits behind an
+executor, so the scheduling logic is tested on the CPU with a fake one.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from concurrent.futures import Future
+from typing import Any, Callable, Optional
+
+
+@dataclasses.dataclass
+class Request:
+    """One search problem.  `make` builds the device inputs (img, var, mask) when
+    the request is admitted; t, vel, psf are host arrays; k results per pixel
+    are kept (k_cand >= k candidates are searched)."""
+    rid: int
+    shape: tuple            # (n_img, h, w)
+    t: Any
+    vel: Any
+    psf: Any
+    k: int
+    make: Callable[[], tuple]
+    k_cand: Optional[int] = None
+    arrival: float = 0.0    # set by submit() unless given
+
+
+@dataclasses.dataclass
+class Done:
+    """What a request's future resolves to."""
+    rid: int
+    result: Any             # executor-specific (device tensors for the GPU executor)
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    def __init__(self, executor, budget_bytes: int, max_batch: int = 64,
+                 max_inflight: int = 2, poll_s: float = 2e-4):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_batch = max_batch
+        self.max_inflight = max_inflight
+        self.poll_s = poll_s
+        self._lock = threading.Condition()
+        self._pending = collections.deque()     # (req, future)
+        self._ready = []                        # prepared, not launched: (req, fut, handle, t_adm)
+        self._inflight = collections.deque()    # (token, [(req, fut, handle, t_adm)])
+        self._in_use = 0
+        self._peak = 0
+        self._stop = False
+        self._thread = None
+        self.batches = []                       # sizes of launched batches
+
+    # -- client side ---------------------------------------------------------
+    def submit(self, req: Request) -> Future:
+        fut = Future()
+        if not req.arrival:
+            req.arrival = time.perf_counter()
+        if self.ex.footprint(req) > self.budget:
+            fut.set_exception(MemoryError(
+                f"request {req.rid} needs {self.ex.footprint(req)} bytes, budget {self.budget}"))
+            return fut
+        with self._lock:
+            self._pending.append((req, fut))
+            self._lock.notify()
+        return fut
+
+    @property
+    def bytes_in_use(self) -> int:
+        return self._in_use
+
+    @property
+    def peak_bytes(self) -> int:
+        return self._peak
+
+    # -- scheduler -----------------------------------------------------------
+    def start(self):
+        self._thread = threading.Thread(target=self._loop, name="kbmi-serve", daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self):
+        with self._lock:
+            self._stop = True
+            self._lock.notify()
+        if self._thread is not None:
+            self._thread.join()
+
+    def idle(self) -> bool:
+        with self._lock:
+            return not (self._pending or self._ready or self._inflight)
+
+    def _admit(self):
+        """Admit pending requests in order while they fit the budget."""
+        admitted = []
+        with self._lock:
+            while self._pending:
+                req, fut = self._pending[0]
+                need = self.ex.footprint(req)
+                if self._in_use + need > self.budget:
+                    break
+                self._pending.popleft()
+                self._in_use += need
+                self._peak = max(self._peak, self._in_use)
+                admitted.append((req, fut, need))
+        for req, fut, need in admitted:
+            t_adm = time.perf_counter()
+            try:
+                handle = self.ex.prepare(req)
+            except Exception as e:               # isolate a failing request
+                self._release_bytes(need)
+                fut.set_exception(e)
+                continue
+            self._ready.append((req, fut, handle, t_adm))
+
+    def _release_bytes(self, n):
+        with self._lock:
+            self._in_use -= n
+            self._lock.notify()
+
+    def _launch(self):
+        while self._ready and len(self._inflight) < self.max_inflight:
+            batch, self._ready = self._ready[:self.max_batch], self._ready[self.max_batch:]
+            try:
+                token = self.ex.launch([h for _, _, h, _ in batch])
+            except Exception as e:
+                # A batch that cannot be launched fails its members only.
+                for req, fut, h, _ in batch:
+                    self.ex.release(h)
+                    self._release_bytes(self.ex.footprint(req))
+                    fut.set_exception(e)
+                continue
+            self.batches.append(len(batch))
+            self._inflight.append((token, batch))
+
+    def _complete(self) -> bool:
+        progressed = False
+        while self._inflight and self.ex.done(self._inflight[0][0]):
+            token, batch = self._inflight.popleft()
+            t_done = time.perf_counter()
+            for req, fut, h, t_adm in batch:
+                try:
+                    res = self.ex.result(h)
+                except Exception as e:
+                    fut.set_exception(e)
+                else:
+                    fut.set_result(Done(req.rid, res, req.arrival, t_adm, t_done))
+                self.ex.release(h)
+                self._release_bytes(self.ex.footprint(req))
+            progressed = True
+        return progressed
+
+    def _loop(self):
+        while True:
+            with self._lock:
+                if self._stop and not (self._pending or self._ready or self._inflight):
+                    return
+            self._admit()
+            self._launch()
+            if not self._complete():
+                with self._lock:
+                    if not (self._pending or self._ready or self._inflight) and not self._stop:
+                        self._lock.wait(0.05)
+                if self._inflight:
+                    time.sleep(self.poll_s)
+
+
+# ---------------------------------------------------------------------------
+# Device executor.
+# ---------------------------------------------------------------------------
+
+def footprint_bytes(n_img, h, w, n_vel, k, k_cand, lp=None) -> int:
+    """Device bytes one request holds while admitted: inputs (img, var, mask),
+    float32 planes (+ the 16-bit copy), candidates, results, workspace."""
+    px = h * w
+    inputs = n_img * px * 9
+    planes = n_img * px * (8 + (4 if lp else 0))
+    cand = px * k_cand * 14
+    out = px * k * 14
+    ws = (((n_img + 15) // 16) * 16 * n_vel * 8) + 4 * n_vel + 4096
+    return inputs + planes + cand + out + ws
+
+
+class GpuExecutor:
+    """Runs requests with libkbmi on one HIP device.  Batches go to the
+    device streams round-robin; results stay on the device."""
+
+    def __init__(self, device="cuda:0", lp=None, streams=2):
+        import torch
+        from . import lib
+        self.torch, self.lib = torch, lib
+        self.dev = torch.device(device)
+        self.lp = lp
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
+        self._next = 0
+
+    def footprint(self, req: Request) -> int:
+        n, h, w = req.shape
+        kc = req.k_cand or req.k
+        return footprint_bytes(n, h, w, len(req.vel), req.k, kc, self.lp)
+
+    def prepare(self, req: Request):
+        torch, lib = self.torch, self.lib
+        s = self.streams[self._next % len(self.streams)]
+        with torch.cuda.stream(s):
+            img, var, mask = req.make()
+            n, h, w = img.shape
+            kc = req.k_cand or req.k
+            if self.lp is None:
+                planes = lib.make_psi_phi(img, var, mask, req.psf)
+                src, sc = planes, None
+            else:
+                planes, src, sc = lib.make_psi_phi(img, var, mask, req.psf, lp=self.lp)
+            cand = lib.alloc_candidates(h, w, kc, self.dev)
+            out = lib.alloc_candidates(h, w, req.k, self.dev)
+            ws = lib.alloc_workspace(n, h, w, len(req.vel), self.dev)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return dict(req=req, img=img, var=var, mask=mask, planes=planes, src=src, scale=sc,
+                    cand=cand, out=out, ws=ws, prepared=ev, stream=s)
+
+    def launch(self, handles):
+        torch, lib = self.torch, self.lib
+        s = self.streams[self._next % len(self.streams)]
+        self._next += 1
+        groups = collections.defaultdict(list)      # one batched launch per k_cand
+        for hd in handles:
+            groups[hd["cand"][0].shape[-1]].append(hd)
+        with torch.cuda.stream(s):
+            for hd in handles:
+                s.wait_event(hd["prepared"])
+            for kc, hs in groups.items():
+                jobs = [dict(planes=hd["src"], t=hd["req"].t, vel=hd["req"].vel,
+                             out=hd["cand"], lp_scale=hd["scale"]) for hd in hs]
+                lib.search_batch(jobs, kc, stream=s)
+                for hd in hs:
+                    n = hd["img"].shape[0]
+                    rescore = None if self.lp is None else (hd["planes"], hd["req"].t,
+                                                            hd["req"].vel, hd["ws"])
+                    lib.topk(hd["cand"], hd["req"].k, n, out=hd["out"], stream=s,
+                             rescore=rescore)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        for hd in handles:
+            hd["stream"] = s
+        return ev
+
+    def done(self, token) -> bool:
+        return token.query()
+
+    def result(self, handle):
+        return handle["out"]
+
+    def release(self, handle):
+        # Tensors return to torch's caching allocator once unreferenced; make
+        # the allocator aware of the stream that used them.
+        s = handle["stream"]
+        for key in ("img", "var", "mask", "planes", "src", "scale", "ws"):
+            t = handle.get(key)
+            if t is not None:
+                t.record_stream(s)
+        for t in handle["cand"]:
+            t.record_stream(s)
+        handle.clear()

@@ -155,3 +155,23 @@ def test_workspace_size():
     assert nb % 256 == 0
     assert lib.search_workspace_bytes(0, 8, 8, 600) == 0
     assert lib.search_workspace_bytes(3, 0, 8, 600) == 0
+
+
+def test_batch_rejects_bad_jobs_before_enqueue():
+    L = lib.load()
+    fake = 1 << 20
+    t = np.array([0.0, 1.0, 2.0])
+    v = np.zeros((4, 2))
+    good = lib.KbJob(fake, None, 3, 8, 8, t.ctypes.data, v.ctypes.data, 4, fake, fake, fake, fake)
+    bad_t = np.array([0.0, 2.0, 1.0])
+    bad = lib.KbJob(fake, None, 3, 8, 8, bad_t.ctypes.data, v.ctypes.data, 4, fake, fake, fake,
+                    fake)
+    arr = (lib.KbJob * 2)(good, bad)
+    st = L.kb_search_batch(ctypes.addressof(arr), 2, 0, 2, fake, 1 << 20, None)
+    assert st == lib.KB_EINVAL and "job 1" in L.kb_last_error().decode()
+    arr = (lib.KbJob * 1)(good)
+    assert L.kb_search_batch(ctypes.addressof(arr), 1, 0, 5, fake, 1 << 20, None) == lib.KB_EINVAL
+    assert L.kb_search_batch(ctypes.addressof(arr), 0, 0, 2, fake, 1 << 20, None) == lib.KB_EINVAL
+    assert L.kb_search_batch(ctypes.addressof(arr), 1, 1, 2, fake, 1 << 20, None) == lib.KB_EINVAL
+    assert L.kb_search_batch(ctypes.addressof(arr), 1, 0, 2, fake, 16, None) == lib.KB_ENOMEM
+    assert L.kb_search_batch_workspace_bytes(ctypes.addressof(arr), 1) > 0

@@ -338,3 +338,31 @@ def test_shorter_list_is_prefix_of_longer(torch_dev, lp):
     torch.cuda.synchronize()
     for a, b in zip(parity.to_numpy(with_census), parity.to_numpy(without)):
         assert np.ascontiguousarray(a).tobytes() == np.ascontiguousarray(b[..., :8]).tobytes()
+
+
+@pytest.mark.parametrize("lp", [None, "f16"])
+def test_batched_search_equals_solo(torch_dev, lp):
+    """kb_search_batch over stacks of uneven size (images, frame, velocities)
+    must give every stack exactly (bitwise) what kb_search gives it alone."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    dev = torch.device("cuda:0")
+    k = 6
+    shapes = [(5, 40, 70, 30), (17, 33, 130, 50), (3, 64, 64, 12), (9, 1, 200, 20),
+              (1, 20, 20, 7), (12, 50, 90, 64)]
+    jobs, solos = [], []
+    for q, (n, h, w, nv) in enumerate(shapes):
+        s = synth.random_stack(60 + q, n=n, h=h, w=w, n_vel=nv, k=k, psf_size=5, vmax=max(h, w))
+        img, var, mask = (torch.from_numpy(a).to(dev) for a in (s.img, s.var, s.mask))
+        if lp is None:
+            src, sc = lib.make_psi_phi(img, var, mask, s.psf), None
+        else:
+            _, src, sc = lib.make_psi_phi(img, var, mask, s.psf, lp=lp)
+        solos.append(lib.search(src, s.t, s.vel, k, lp_scale=sc))
+        out = lib.alloc_candidates(h, w, k, dev)
+        jobs.append(dict(planes=src, t=s.t, vel=s.vel, out=out, lp_scale=sc))
+    lib.search_batch(jobs, k)
+    torch.cuda.synchronize()
+    for jb, solo in zip(jobs, solos):
+        for a, b in zip(parity.to_numpy(jb["out"]), parity.to_numpy(solo)):
+            assert a.tobytes() == b.tobytes()
