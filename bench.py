@@ -28,7 +28,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_TIE_F32 = 8.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1901_02492_amd", "csrc", "kbmi_kernels.hip")
+# The search kernel's sources: a counter profile is valid only for these bytes.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1901_02492_amd", "csrc", f)
+                  for f in ("kbmi_device.h", "kbmi_search.hip")]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "search_kernel_survey_15x4096x4096_v600_k50.md")
 
 
@@ -38,11 +40,15 @@ def measured_traffic():
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
-        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(f, "rb").read())
+        src = h.hexdigest()
     except OSError:
         return None
-    fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("kernel_source_sha256:", "traffic_bytes_per_launch:")))
+    fields = dict(line.strip().split(":", 1) for line in text.splitlines()
+                  if line.strip().startswith(("kernel_source_sha256:",
+                                              "traffic_bytes_per_launch:")))
     if fields.get("kernel_source_sha256", "").strip() != src:
         return None
     try:
