@@ -17,13 +17,18 @@
 #ifndef KBMI_QUEUE
 #define KBMI_QUEUE 16           // queued candidates per lane before a merge
 #endif
+#ifndef KBMI_PREFETCH
+#define KBMI_PREFETCH 1         // single-stack search: fetch the next table row early
+#endif
 
 // List lengths compiled for the search: every even length up to KB_MAX_KCAND
 // (each slot costs registers and compare-and-swap work on every insertion).
+#ifndef KB_SEARCH_KM_LIST
 #define KB_SEARCH_KM_LIST(X)                                                              \
     X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) \
     X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50) X(52) X(54) X(56) X(58)  \
     X(60) X(62) X(64)
+#endif
 
 namespace kbmi {
 
@@ -32,7 +37,7 @@ struct StackView {
     const void *planes;        // [n_img][h][w] (psi, phi) pairs of the plane format
     const float2 *inv_scale;   // 16-bit planes: (1/s_psi, 1/s_phi) per image, padded with 0
     int n_img, h, w;
-    const int2 *disp;          // displacement rows in visiting order, `disp_stride` pairs each
+    const GatherEntry *disp;   // gather-table rows in visiting order, `disp_stride` entries each
     int disp_stride;
     const int32_t *vel_index;  // original index of each visited velocity
     int n_vel, k_cand;
@@ -45,7 +50,7 @@ struct StackView {
 struct BatchJob {
     const void *planes;
     const float2 *inv_scale;
-    const int2 *disp;
+    const GatherEntry *disp;
     const int32_t *vel_index;
     float *cand_nu, *cand_alpha;
     int32_t *cand_vel;
@@ -67,20 +72,39 @@ kb_status launch_search_batch_f16(int km, const BatchJob *jobs, int n_jobs, int 
 kb_status launch_search_batch_bf16(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
                                    int k_cand, hipStream_t s);
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) i32x4 global_i32x4;
+typedef __attribute__((address_space(1))) f32x4 global_f32x4;
+typedef __attribute__((address_space(1))) const int32_t global_i32;
+
+// Raw buffer loads with the descriptor as four plain words.
+__device__ u32x2 raw_load_b64(i32x4 rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v2i32");
+__device__ uint32_t raw_load_b32(i32x4 rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.i32");
+
 namespace {
 
 // ---------------------------------------------------------------------------
-// Raw buffer access (stride 0: an access is out of range when its byte offset
-// is >= the buffer's record count, and then a load returns 0).
+// Raw buffer access.  A descriptor is four scalar words: the 48-bit base
+// address, the record count in bytes (stride 0: an access is out of range when
+// its byte offset is >= the record count, and then a load returns 0 without
+// touching memory), and the format word.  The loads take the descriptor as a
+// plain vector so that building one costs no masking.
 // ---------------------------------------------------------------------------
 constexpr int kBufferFlags = 0x00020000;
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
-                                             kBufferFlags);
+
+__device__ inline i32x4 buffer_words(uint64_t base, uint32_t bytes) {
+    i32x4 r;
+    r.x = (int)(uint32_t)base;
+    r.y = (int)(uint32_t)(base >> 32);
+    r.z = (int)bytes;
+    r.w = kBufferFlags;
+    return r;
 }
-
 
 // ---------------------------------------------------------------------------
 // Candidate keys.  A candidate is ordered by (nu descending, j ascending); the
@@ -102,6 +126,24 @@ __device__ inline float nu_from_order_bits(uint32_t o) {
 __device__ inline uint64_t make_key(float nu, int j, uint32_t nobs) {
     return ((uint64_t)nu_order_bits(nu) << 32) |
            (uint64_t)(((uint32_t)(0xFFFF - j) << 16) | (nobs & 0xFFFFu));
+}
+
+// Scores of one trajectory (Sec. 2.1.5): nu = Psi / sqrt(Phi) and
+// alpha = Psi / Phi, both from the hardware reciprocal square root r of Phi
+// (within 1 ulp for normal inputs; Phi below 2^-100 is scaled by 2^64 first,
+// so no denormal reaches it): nu = Psi * r, alpha = nu * r.  Phi = 0 (no valid
+// observation) gives nu = -inf and alpha = 0.  Every kernel scores with these
+// functions, so equal sums give bitwise equal scores.
+__device__ inline float inv_sqrt_phi(float F) {
+    const bool tiny = F < 0x1p-100f;
+    const float r = __builtin_amdgcn_rsqf(tiny ? F * 0x1p64f : F);
+    return tiny ? r * 0x1p32f : r;
+}
+__device__ inline float score_nu(float P, float F, float r) {
+    return F > 0.f ? P * r : -INFINITY;
+}
+__device__ inline float score_alpha(float nu, float F, float r) {
+    return F > 0.f ? nu * r : 0.f;
 }
 
 // Start-pixel tiles: one wave = 64 adjacent pixels of one row.  Tiles are
@@ -189,10 +231,10 @@ constexpr int search_lds_words() {
 
 // The search of one tile (start row `row`, start columns seg*64 .. seg*64+63).
 // All scalar arguments are wave-uniform.
-template <int KM, int NB, int PB, int FMT>
+template <int KM, int NB, int PB, int FMT, bool PF>
 __device__ __forceinline__ void search_tile(
     uint32_t *lds, const void *__restrict__ planes, const float2 *__restrict__ inv_scale,
-    int n_img, int h, int w, const int2 *__restrict__ disp, int disp_stride,
+    int n_img, int h, int w, const GatherEntry *__restrict__ disp, int disp_stride,
     const int32_t *__restrict__ vel_index, int n_vel, int k_cand, int row, int seg,
     float *__restrict__ cand_nu, float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
     int16_t *__restrict__ cand_nobs) {
@@ -217,33 +259,36 @@ __device__ __forceinline__ void search_tile(
     uint64_t thr = 0;   // admission threshold (list tail at the last merge)
     int nq = 0;         // queued candidates of this lane
 
-    // Issue the loads of images [i0, i0 + NB) of visited velocity jj.  The
-    // table row is fetched whole first (its padding entries lie outside the
-    // frame); rows outside the frame get a zero-length buffer, so their loads
-    // return 0 and add nothing, with no branch.
-    auto issue = [&](int jj, int i0, LoadT(&v)[NB]) {
-        const int4 *t4 = reinterpret_cast<const int4 *>(disp + (size_t)jj * disp_stride + i0);
-        int4 dd[NB / 2];
+    const global_i32 *visit = (const global_i32 *)(const void *)vel_index;
+    // Byte address of the start row in image 0; a table entry's offset moves
+    // it to the displaced row of its image.
+    const uint64_t row0 = reinterpret_cast<uint64_t>(planes) + (uint64_t)row * row_bytes;
+    (void)img_bytes;
+    // Fetch entries [i0, i0 + NB) of table row jj (wide scalar loads).
+    // The table is global memory (spelled out: in the batched search its
+    // address comes from a descriptor, and only global loads become scalar).
+    auto fetch = [&](int jj, int i0, i32x4(&e)[NB]) {
+        const global_i32x4 *t4 =
+            (const global_i32x4 *)(const void *)(disp + (size_t)jj * disp_stride + i0);
 #pragma unroll
-        for (int q = 0; q < NB / 2; ++q) dd[q] = t4[q];
-        // Recomputed per velocity (not hoisted): keeps NB image bases out of
-        // the scalar register file.
-        const char *pbase = reinterpret_cast<const char *>(planes) + (size_t)i0 * img_bytes;
-        asm volatile("" : "+s"(pbase));
+        for (int b = 0; b < NB; ++b) e[b] = t4[b];
+    };
+    // Issue the gathers of one batch of table entries.  A row outside the
+    // frame (padding entries included) gets a zero-length buffer, so its loads
+    // return 0 and add nothing, with no branch.  With a record count of 0 every
+    // lane fails the range check before an address is formed, so the base of
+    // such a buffer (which may point outside the planes) is never dereferenced.
+    auto issue = [&](const i32x4(&e)[NB], LoadT(&v)[NB]) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int dx = (b & 1) ? dd[b / 2].z : dd[b / 2].x;
-            const int dy = (b & 1) ? dd[b / 2].w : dd[b / 2].y;
-            const int yy = row + dy;
+            const int yy = row + e[b].y;
             const bool in_rows = (unsigned)yy < (unsigned)h;
-            const char *rb = pbase + (size_t)b * img_bytes +
-                             (size_t)(in_rows ? yy : 0) * (size_t)row_bytes;
-            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(in_rows ? rb : pbase,
-                                                          in_rows ? row_bytes : 0u);
+            const uint64_t off = ((uint64_t)(uint32_t)e[b].w << 32) | (uint32_t)e[b].z;
+            const i32x4 rs = buffer_words(row0 + off, in_rows ? row_bytes : 0u);
             if constexpr (FMT == KB_F32)
-                v[b] = __builtin_amdgcn_raw_buffer_load_b64(rs, (x0 + dx) * (int)kPix, 0, 0);
+                v[b] = raw_load_b64(rs, (x0 + e[b].x) * (int)kPix, 0, 0);
             else
-                v[b] = __builtin_amdgcn_raw_buffer_load_b32(rs, (x0 + dx) * (int)kPix, 0, 0);
+                v[b] = raw_load_b32(rs, (x0 + e[b].x) * (int)kPix, 0, 0);
         }
     };
     // Sum in image order.  Empty slots hold +0, which leaves every sum
@@ -258,8 +303,8 @@ __device__ __forceinline__ void search_tile(
                 F += __uint_as_float(v[b].y);
             }
         } else {
-            const float4 *sc4 = reinterpret_cast<const float4 *>(inv_scale + i0);
-            float4 ss[NB / 2];
+            const global_f32x4 *sc4 = (const global_f32x4 *)(const void *)(inv_scale + i0);
+            f32x4 ss[NB / 2];
 #pragma unroll
             for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
 #pragma unroll
@@ -276,8 +321,8 @@ __device__ __forceinline__ void search_tile(
         uint32_t c = 0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            if constexpr (FMT == KB_F32) c += v[b].y != 0u;
-            else c += (v[b] >> 16) != 0u;
+            if constexpr (FMT == KB_F32) c += min(v[b].y, 1u);
+            else c += min(v[b] >> 16, 1u);
         }
         return c;
     };
@@ -308,34 +353,60 @@ __device__ __forceinline__ void search_tile(
     // and queue it if it beats the admission threshold.  n_obs sits in the
     // low bits of the key and never decides an order.
     auto finish = [&](int j, float P, float F, uint32_t c) {
-        const float nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
+        const float r = inv_sqrt_phi(F);
+        const float nu = score_nu(P, F, r);
         const uint64_t nk = make_key(nu, j, 0u);
         if (nk > thr) {
             q_hi[nq * 64 + lane] = (uint32_t)(nk >> 32);
             q_lo[nq * 64 + lane] = (uint32_t)nk | c;
-            q_al[nq * 64 + lane] = F > 0.f ? P / F : 0.f;
+            q_al[nq * 64 + lane] = score_alpha(nu, F, r);
             ++nq;
         }
         if (__any(nq == PB)) merge_queue();
     };
 
-    if (n_img <= NB) {
+    if (n_img <= NB && PF) {
+        // The next velocity's table row is fetched while this velocity's
+        // gathers are in flight.
+        i32x4 e[NB];
+        fetch(0, 0, e);
+        int j_next = visit[0];
         for (int jj = 0; jj < n_vel; ++jj) {
-            const int j = vel_index[jj];   // fetched before the gathers are issued
+            const int j = j_next;
             LoadT v[NB];
-            issue(jj, 0, v);
+            issue(e, v);
+            // Keep the next row's fetch right behind the gathers (the scheduler
+            // would otherwise sink it below the sums).
+            __builtin_amdgcn_sched_barrier(0);
+            const int jn = jj + 1 < n_vel ? jj + 1 : jj;
+            fetch(jn, 0, e);
+            j_next = visit[jn];
+            __builtin_amdgcn_sched_barrier(0);
+            float P = 0.f, F = 0.f;
+            accumulate(0, v, P, F);
+            finish(j, P, F, count(v));
+        }
+    } else if (n_img <= NB) {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = visit[jj];
+            i32x4 e[NB];
+            fetch(jj, 0, e);
+            LoadT v[NB];
+            issue(e, v);
             float P = 0.f, F = 0.f;
             accumulate(0, v, P, F);
             finish(j, P, F, count(v));
         }
     } else {
         for (int jj = 0; jj < n_vel; ++jj) {
-            const int j = vel_index[jj];
+            const int j = visit[jj];
             float P = 0.f, F = 0.f;
             uint32_t c = 0;
             for (int i0 = 0; i0 < n_img; i0 += NB) {
+                i32x4 e[NB];
+                fetch(jj, i0, e);
                 LoadT v[NB];
-                issue(jj, i0, v);
+                issue(e, v);
                 accumulate(i0, v, P, F);
                 c += count(v);
             }
@@ -380,14 +451,15 @@ __device__ __forceinline__ void search_tile(
 template <int KM, int NB, int PB, int FMT>
 __global__ __launch_bounds__(64, 2) void search_kernel(
     const void *__restrict__ planes, const float2 *__restrict__ inv_scale, int n_img, int h,
-    int w, const int2 *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
+    int w, const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
     int n_vel, int k_cand, TileMap tiles, float *__restrict__ cand_nu,
     float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
     int16_t *__restrict__ cand_nobs) {
     __shared__ uint32_t lds[search_lds_words<KM, PB>()];
     int row, seg;
     tiles.map(blockIdx.x, row, seg);
-    search_tile<KM, NB, PB, FMT>(lds, planes, inv_scale, n_img, h, w, disp, disp_stride,
+    search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(lds, planes, inv_scale, n_img, h, w, disp,
+                                                     disp_stride,
                                  vel_index, n_vel, k_cand, row, seg, cand_nu, cand_alpha,
                                  cand_vel, cand_nobs);
 }
@@ -414,7 +486,7 @@ __global__ __launch_bounds__(64, 2) void search_batch_kernel(const BatchJob *__r
     int row, seg;
     const int h = jb.h;
     strip_tile(t - jb.block_begin, jb.nseg, h, jb.strip, row, seg);
-    search_tile<KM, 16, PB, FMT>(lds, jb.planes, jb.inv_scale, jb.n_img, h, jb.w, jb.disp,
+    search_tile<KM, 16, PB, FMT, false>(lds, jb.planes, jb.inv_scale, jb.n_img, h, jb.w, jb.disp,
                                  jb.disp_stride, jb.vel_index, jb.n_vel, k_cand, row, seg,
                                  jb.cand_nu, jb.cand_alpha, jb.cand_vel, jb.cand_nobs);
 }

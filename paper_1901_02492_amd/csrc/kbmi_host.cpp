@@ -146,9 +146,41 @@ WorkspaceLayout workspace_layout(int64_t n_img, int64_t h, int64_t w, int64_t n_
 }
 
 size_t table_bytes(int64_t n_img, int64_t n_vel) {
-    const size_t raw = static_cast<size_t>(table_stride(n_img)) * static_cast<size_t>(n_vel) * 2 *
-                       sizeof(int32_t);
+    const size_t raw = static_cast<size_t>(table_stride(n_img)) * static_cast<size_t>(n_vel) *
+                       sizeof(GatherEntry);
     return (raw + 255) & ~static_cast<size_t>(255);
+}
+
+void gather_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel, int64_t h,
+                  int64_t w, int64_t pix_bytes, bool visiting_order, GatherEntry *table,
+                  int32_t *order) {
+    if (visiting_order)
+        velocity_order(vel, n_vel, order);
+    else
+        for (int64_t j = 0; j < n_vel; ++j) order[j] = static_cast<int32_t>(j);
+    std::vector<double> vel_visit(static_cast<size_t>(n_vel) * 2);
+    for (int64_t j = 0; j < n_vel; ++j) {
+        vel_visit[2 * j] = vel[2 * order[j]];
+        vel_visit[2 * j + 1] = vel[2 * order[j] + 1];
+    }
+    std::vector<int32_t> dense(static_cast<size_t>(n_img) * n_vel * 2);
+    displacement_table(t, n_img, vel_visit.data(), n_vel, dense.data(), w, h);
+    // Padding entries (0, h): row + h is outside the frame for every start row.
+    const int64_t stride = table_stride(n_img);
+    const int64_t row_bytes = w * pix_bytes, image_bytes = h * row_bytes;
+    for (int64_t j = 0; j < n_vel; ++j)
+        for (int64_t i = 0; i < stride; ++i) {
+            GatherEntry &e = table[j * stride + i];
+            if (i < n_img) {
+                e.dx = dense[(j * n_img + i) * 2];
+                e.dy = dense[(j * n_img + i) * 2 + 1];
+                e.offset = i * image_bytes + static_cast<int64_t>(e.dy) * row_bytes;
+            } else {
+                e.dx = 0;
+                e.dy = static_cast<int32_t>(h);
+                e.offset = 0;
+            }
+        }
 }
 
 }  // namespace kbmi

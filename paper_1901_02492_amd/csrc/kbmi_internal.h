@@ -31,14 +31,32 @@ void displacement_table(const double *t, int64_t n_img, const double *vel, int64
 // order gives the same result (ranking uses the original index).
 void velocity_order(const double *vel, int64_t n_vel, int32_t *order);
 
-// Device workspace layout: the clamped displacement table in visiting order at
-// offset 0, one row of table_stride(n_img) (dx, dy) pairs per velocity (a
-// multiple of 16; the rows are padded with entries that lie outside the frame
-// so that the search can fetch whole batches of 8 or 16 with wide scalar
-// loads), then the original index of each visited velocity (int32 [n_vel]).
+// One entry of the search's gather table (16 bytes): the displacement (dx, dy)
+// of one image for one velocity, and the byte offset of the displaced row from
+// the start row in the planes, image * image_bytes + dy * row_bytes, so that
+// the search forms a row address with one 64-bit add.
+struct alignas(16) GatherEntry {
+    int32_t dx, dy;
+    int64_t offset;
+};
+static_assert(sizeof(GatherEntry) == 16, "gather entries are fetched as 16-byte words");
+
+// Device workspace layout: the gather table at offset 0, one row of
+// table_stride(n_img) entries per velocity in visiting order (a multiple of
+// 16; rows are padded with entries whose row lies outside the frame, so that
+// the search fetches whole batches of 8 or 16 with wide scalar loads), then the
+// original index of each visited velocity (int32 [n_vel]).
 int64_t table_stride(int64_t n_img);
 size_t table_bytes(int64_t n_img, int64_t n_vel);
 size_t order_bytes(int64_t n_vel);
+
+// Fill `table` (table_bytes(n_img, n_vel) bytes) and `order` (int32 [n_vel])
+// for planes of `pix_bytes` bytes per (psi, phi) pair: velocities in visiting
+// order (or the given order), offsets clamped to the frame extent.  Arguments
+// must already be checked.
+void gather_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel, int64_t h,
+                  int64_t w, int64_t pix_bytes, bool visiting_order, GatherEntry *table,
+                  int32_t *order);
 // Whole workspace of kb_search / kb_topk (byte offsets, 256-byte aligned): the
 // table, the visiting order and the 16-bit search's per-image inverse scales
 // (float2 [table_stride]).

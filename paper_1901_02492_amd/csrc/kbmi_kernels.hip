@@ -266,7 +266,7 @@ __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
     int64_t npix, int h, int w, int n_img, const float2 *__restrict__ planes,
-    const int2 *__restrict__ table, int stride, int n_vel, int k_cand, int k,
+    const GatherEntry *__restrict__ table, int stride, int n_vel, int k_cand, int k,
     const int32_t *__restrict__ cand_vel, float *__restrict__ nu, float *__restrict__ alpha,
     int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
     __shared__ uint64_t s_key[TK_THREADS];
@@ -284,15 +284,15 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
     const bool scored = active && j >= 0 && j < n_vel;
     if (scored) {
         const int y0 = (int)(p / w), x0 = (int)(p - (int64_t)y0 * w);
-        const int2 *tj = table + (size_t)j * (size_t)stride;
+        const GatherEntry *tj = table + (size_t)j * (size_t)stride;
         float P = 0.f, F = 0.f;
         for (int i0 = 0; i0 < n_img; i0 += 8) {
             float2 v[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int i = i0 + b;
-                const int2 d = tj[i < n_img ? i : 0];
-                const int y = y0 + d.y, x = x0 + d.x;
+                const GatherEntry &d = tj[i < n_img ? i : 0];
+                const int y = y0 + d.dy, x = x0 + d.dx;
                 const bool ok = i < n_img && (unsigned)y < (unsigned)h && (unsigned)x < (unsigned)w;
                 const size_t idx = ok ? ((size_t)i * h + y) * (size_t)w + x : 0;
                 const float2 raw = planes[idx];
@@ -305,8 +305,9 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
                 c += __float_as_uint(v[b].y) != 0u;
             }
         }
-        v_nu = F > 0.f ? P / sqrtf(F) : -INFINITY;
-        v_al = F > 0.f ? P / F : 0.f;
+        const float r = inv_sqrt_phi(F);
+        v_nu = score_nu(P, F, r);
+        v_al = score_alpha(v_nu, F, r);
         key = make_key(v_nu, j, c);
     }
     s_key[t] = key;
@@ -337,7 +338,7 @@ __global__ void inv_scale_kernel(const float *__restrict__ scale, int n_img, int
 }
 
 kb_status launch_topk_rescore(int64_t npix, int h, int w, int n_img, const float2 *planes,
-                              const int2 *table, int stride, int n_vel, int k_cand, int k,
+                              const GatherEntry *table, int stride, int n_vel, int k_cand, int k,
                               const int32_t *cv,
                               float *nu, float *al, int32_t *vi, int16_t *no, hipStream_t stream) {
     const int64_t ppb = TK_THREADS / k_cand;
@@ -369,39 +370,20 @@ kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
     return KB_OK;
 }
 
-// Copy the clamped displacement table into the workspace.  The host copy is
-// pageable and temporary, so the call waits until it has reached the device.
+// Copy the gather table (for planes of `pix_bytes` bytes per pair) and the
+// visiting order into the workspace.  The host copies are pageable and
+// temporary, so the call waits until they have reached the device.
 kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
-                       int64_t h, int64_t w, void *workspace, hipStream_t stream,
-                       bool visiting_order = true) {
-    // Velocities in visiting order, then the table of the reordered grid.
-    std::vector<int32_t> order(static_cast<size_t>(n_vel));
-    if (visiting_order)
-        velocity_order(vel, n_vel, order.data());
-    else
-        for (int64_t j = 0; j < n_vel; ++j) order[j] = static_cast<int32_t>(j);
-    std::vector<double> vel_visit(static_cast<size_t>(n_vel) * 2);
-    for (int64_t j = 0; j < n_vel; ++j) {
-        vel_visit[2 * j] = vel[2 * order[j]];
-        vel_visit[2 * j + 1] = vel[2 * order[j] + 1];
-    }
-    std::vector<int32_t> dense(static_cast<size_t>(n_img) * n_vel * 2);
-    displacement_table(t, n_img, vel_visit.data(), n_vel, dense.data(), w, h);
-    // Pad each row to the stride with (0, h): row + h is outside the frame.
-    const int64_t stride = table_stride(n_img);
-    std::vector<int32_t> table(static_cast<size_t>(stride) * n_vel * 2);
-    for (int64_t j = 0; j < n_vel; ++j)
-        for (int64_t i = 0; i < stride; ++i) {
-            const bool real = i < n_img;
-            table[(j * stride + i) * 2] = real ? dense[(j * n_img + i) * 2] : 0;
-            table[(j * stride + i) * 2 + 1] = real ? dense[(j * n_img + i) * 2 + 1] : (int32_t)h;
-        }
-    char *ws = static_cast<char *>(workspace);
-    hipError_t e = hipMemcpyAsync(ws, table.data(), table.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(ws + table_bytes(n_img, n_vel), order.data(),
-                           order.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+                       int64_t h, int64_t w, int64_t pix_bytes, void *workspace,
+                       hipStream_t stream, bool visiting_order = true) {
+    const size_t tb = table_bytes(n_img, n_vel);
+    std::vector<char> host(tb + static_cast<size_t>(n_vel) * sizeof(int32_t));
+    gather_table(t, n_img, vel, n_vel, h, w, pix_bytes, visiting_order,
+                 reinterpret_cast<GatherEntry *>(host.data()),
+                 reinterpret_cast<int32_t *>(host.data() + tb));
+    // The order follows the (256-byte rounded) table directly in the workspace.
+    hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice,
+                                  stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess)
         return fail(KB_EDEVICE, "displacement table upload failed: %s", hipGetErrorString(e));
@@ -495,7 +477,7 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     if (workspace_bytes < ws_need)
         return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need, workspace_bytes);
     hipStream_t s = (hipStream_t)stream;
-    st = upload_table(t, n_img, vel, n_vel, h, w, workspace, s);
+    st = upload_table(t, n_img, vel, n_vel, h, w, dtype == KB_F32 ? 8 : 4, workspace, s);
     if (st != KB_OK) return st;
     const int kc = (int)k_cand;
     char *wsb = static_cast<char *>(workspace);
@@ -506,7 +488,7 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     sv.n_img = (int)n_img;
     sv.h = (int)h;
     sv.w = (int)w;
-    sv.disp = reinterpret_cast<const int2 *>(wsb + lay.table);
+    sv.disp = reinterpret_cast<const GatherEntry *>(wsb + lay.table);
     sv.disp_stride = (int)table_stride(n_img);
     sv.vel_index = reinterpret_cast<const int32_t *>(wsb + lay.order);
     sv.n_vel = (int)n_vel;
@@ -558,11 +540,11 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
             return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need,
                         workspace_bytes);
         hipStream_t s = (hipStream_t)stream;
-        st = upload_table(t, n_img, vel, n_vel, h, w, workspace, s, false);
+        st = upload_table(t, n_img, vel, n_vel, h, w, 8, workspace, s, false);
         if (st != KB_OK) return st;
         return launch_topk_rescore(npix, (int)h, (int)w, (int)n_img,
                                    reinterpret_cast<const float2 *>(psi_phi_f32),
-                                   reinterpret_cast<const int2 *>(workspace),
+                                   reinterpret_cast<const GatherEntry *>(workspace),
                                    (int)table_stride(n_img), (int)n_vel, (int)k_cand, (int)k,
                                    cand_vel, nu, alpha, vel_idx, nobs, s);
     }
@@ -658,29 +640,14 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
     int block_begin = 0;
     for (int64_t q = 0; q < n_jobs; ++q) {
         const kb_job &j = jobs[q];
-        std::vector<int32_t> order(static_cast<size_t>(j.n_vel));
-        velocity_order(j.vel, j.n_vel, order.data());
-        std::vector<double> vel_visit(static_cast<size_t>(j.n_vel) * 2);
-        for (int64_t v = 0; v < j.n_vel; ++v) {
-            vel_visit[2 * v] = j.vel[2 * order[v]];
-            vel_visit[2 * v + 1] = j.vel[2 * order[v] + 1];
-        }
-        std::vector<int32_t> dense(static_cast<size_t>(j.n_img) * j.n_vel * 2);
-        displacement_table(j.t, j.n_img, vel_visit.data(), j.n_vel, dense.data(), j.w, j.h);
+        gather_table(j.t, j.n_img, j.vel, j.n_vel, j.h, j.w, dtype == KB_F32 ? 8 : 4, true,
+                     reinterpret_cast<GatherEntry *>(host.data() + lay.table[q]),
+                     reinterpret_cast<int32_t *>(host.data() + lay.order[q]));
         const int64_t stride = table_stride(j.n_img);
-        int32_t *table = reinterpret_cast<int32_t *>(host.data() + lay.table[q]);
-        for (int64_t v = 0; v < j.n_vel; ++v)
-            for (int64_t i = 0; i < stride; ++i) {
-                const bool real = i < j.n_img;
-                table[(v * stride + i) * 2] = real ? dense[(v * j.n_img + i) * 2] : 0;
-                table[(v * stride + i) * 2 + 1] =
-                    real ? dense[(v * j.n_img + i) * 2 + 1] : (int32_t)j.h;
-            }
-        std::memcpy(host.data() + lay.order[q], order.data(), order.size() * sizeof(int32_t));
         BatchJob &d = desc[q];
         d.planes = j.planes;
         d.inv_scale = reinterpret_cast<const float2 *>(ws + lay.inv_scale[q]);
-        d.disp = reinterpret_cast<const int2 *>(ws + lay.table[q]);
+        d.disp = reinterpret_cast<const GatherEntry *>(ws + lay.table[q]);
         d.vel_index = reinterpret_cast<const int32_t *>(ws + lay.order[q]);
         d.cand_nu = j.cand_nu;
         d.cand_alpha = j.cand_alpha;
