@@ -108,15 +108,21 @@ __device__ inline i32x4 buffer_words(uint64_t base, uint32_t bytes) {
 
 // ---------------------------------------------------------------------------
 // Candidate keys.  A candidate is ordered by (nu descending, j ascending); the
-// 64-bit key (order-preserving bits of nu) << 32 | (0xFFFF - j) << 16 | n_obs
+// 63-bit key (order-preserving bits of nu) << 31 | (0xFFFF - j) << 15 | n_obs
 // compares the same way as unsigned integers.  n_obs never decides an order
 // because j is unique within a pixel.  Key 0 is below every real candidate
 // (nu = -inf maps to 0x007FFFFF) and marks an empty slot.
+//
+// Read as an IEEE double, such a key is non-negative (bit 63 is clear) and
+// finite (the order bits are clamped to those of +inf, so the exponent field
+// never reaches all ones), and doubles of that kind order exactly like their
+// bit patterns: the FP64 max/min instructions move a key in one instruction.
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t nu_order_bits(float nu) {
     uint32_t u = __float_as_uint(nu);
     if (u == 0x80000000u) u = 0u;   // -0 ranks equal to +0
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return min(o, 0xFF800000u);     // nothing ranks above +inf
 }
 
 __device__ inline float nu_from_order_bits(uint32_t o) {
@@ -124,8 +130,23 @@ __device__ inline float nu_from_order_bits(uint32_t o) {
 }
 
 __device__ inline uint64_t make_key(float nu, int j, uint32_t nobs) {
-    return ((uint64_t)nu_order_bits(nu) << 32) |
-           (uint64_t)(((uint32_t)(0xFFFF - j) << 16) | (nobs & 0xFFFFu));
+    return ((uint64_t)nu_order_bits(nu) << 31) |
+           (uint64_t)(((uint32_t)(0xFFFF - j) << 15) | (nobs & 0x7FFFu));
+}
+__device__ inline float key_nu(uint64_t k) { return nu_from_order_bits((uint32_t)(k >> 31)); }
+__device__ inline int32_t key_vel(uint64_t k) {
+    return 0xFFFF - (int32_t)((uint32_t)(k >> 15) & 0xFFFFu);
+}
+__device__ inline int32_t key_nobs(uint64_t k) { return (int32_t)((uint32_t)k & 0x7FFFu); }
+
+// k, n <- max(k, n), min(k, n) as keys, in place.
+__device__ inline void key_exchange(uint64_t &k, uint64_t &n) {
+    double kd = __builtin_bit_cast(double, k), t;
+    asm("v_min_f64 %0, %1, %2\n\tv_max_f64 %1, %1, %2"
+        : "=&v"(t), "+v"(kd)
+        : "v"(__builtin_bit_cast(double, n)));
+    k = __builtin_bit_cast(uint64_t, kd);
+    n = __builtin_bit_cast(uint64_t, t);
 }
 
 // Scores of one trajectory (Sec. 2.1.5): nu = Psi / sqrt(Phi) and
@@ -294,19 +315,23 @@ __device__ __forceinline__ void search_tile(
     // Sum in image order.  Empty slots hold +0, which leaves every sum
     // unchanged.  16-bit values are decoded and unscaled by an exact power of
     // two inside the FMA (the product is exact, so the sum rounds once).
-    auto accumulate = [&](int i0, const LoadT(&v)[NB], float &P, float &F) {
+    // 16-bit planes: the inverse scales (1/s_psi, 1/s_phi) of images
+    // [i0, i0 + NB), uniform values.
+    typedef f32x4 Scales[NB / 2];
+    auto load_scales = [&](int i0, Scales &ss) {
+        const global_f32x4 *sc4 = (const global_f32x4 *)(const void *)(inv_scale + i0);
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
+    };
+    auto accumulate = [&](const Scales &ss, const LoadT(&v)[NB], float &P, float &F) {
         if constexpr (FMT == KB_F32) {
-            (void)i0;
+            (void)ss;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 P += __uint_as_float(v[b].x);
                 F += __uint_as_float(v[b].y);
             }
         } else {
-            const global_f32x4 *sc4 = (const global_f32x4 *)(const void *)(inv_scale + i0);
-            f32x4 ss[NB / 2];
-#pragma unroll
-            for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const float isp = (b & 1) ? ss[b / 2].z : ss[b / 2].x;
@@ -326,13 +351,14 @@ __device__ __forceinline__ void search_tile(
         }
         return c;
     };
+    // One pass of the insertion network: slot s keeps the larger key, the
+    // smaller moves on (keys within a pixel are distinct, so one compare
+    // decides where alpha goes).
     auto insert = [&](uint64_t nk, float a) {
 #pragma unroll
         for (int s = 0; s < KM; ++s) {
             const bool c = nk > key[s];
-            const uint64_t tk = c ? key[s] : nk;
-            key[s] = c ? nk : key[s];
-            nk = tk;
+            key_exchange(key[s], nk);
             const float ta = c ? al[s] : a;
             al[s] = c ? a : al[s];
             a = ta;
@@ -365,6 +391,16 @@ __device__ __forceinline__ void search_tile(
         if (__any(nq == PB)) merge_queue();
     };
 
+    // With all images in one batch the scales are loop-invariant: they are
+    // kept in vector registers (the scalar file holds the table row).
+    Scales ss0 = {};
+    if constexpr (FMT != KB_F32) {
+        if (n_img <= NB) {
+            load_scales(0, ss0);
+#pragma unroll
+            for (int q = 0; q < NB / 2; ++q) asm volatile("" : "+v"(ss0[q]));
+        }
+    }
     if (n_img <= NB && PF) {
         // The next velocity's table row is fetched while this velocity's
         // gathers are in flight.
@@ -383,7 +419,7 @@ __device__ __forceinline__ void search_tile(
             j_next = visit[jn];
             __builtin_amdgcn_sched_barrier(0);
             float P = 0.f, F = 0.f;
-            accumulate(0, v, P, F);
+            accumulate(ss0, v, P, F);
             finish(j, P, F, count(v));
         }
     } else if (n_img <= NB) {
@@ -394,7 +430,7 @@ __device__ __forceinline__ void search_tile(
             LoadT v[NB];
             issue(e, v);
             float P = 0.f, F = 0.f;
-            accumulate(0, v, P, F);
+            accumulate(ss0, v, P, F);
             finish(j, P, F, count(v));
         }
     } else {
@@ -407,7 +443,9 @@ __device__ __forceinline__ void search_tile(
                 fetch(jj, i0, e);
                 LoadT v[NB];
                 issue(e, v);
-                accumulate(i0, v, P, F);
+                Scales ss = {};
+                if constexpr (FMT != KB_F32) load_scales(i0, ss);
+                accumulate(ss, v, P, F);
                 c += count(v);
             }
             finish(j, P, F, c);
@@ -425,12 +463,11 @@ __device__ __forceinline__ void search_tile(
     for (int field = 0; field < 4; ++field) {
 #pragma unroll
         for (int s = 0; s < KM; ++s) {
-            const uint32_t hi = (uint32_t)(key[s] >> 32), lo = (uint32_t)key[s];
             uint32_t v;
-            if (field == 0) v = __float_as_uint(nu_from_order_bits(hi));
+            if (field == 0) v = __float_as_uint(key_nu(key[s]));
             else if (field == 1) v = __float_as_uint(al[s]);
-            else if (field == 2) v = (uint32_t)(0xFFFF - (int)(lo >> 16));
-            else v = lo & 0xFFFFu;
+            else if (field == 2) v = (uint32_t)key_vel(key[s]);
+            else v = (uint32_t)key_nobs(key[s]);
             lds[lane * KM + s] = v;
         }
         __syncthreads();
