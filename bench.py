@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import multiprocessing as mp
 import os
 import sys
@@ -112,8 +113,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="survey", choices=["survey", "small"])
+    ap.add_argument("--workload", default="survey", choices=["survey", "small", "serve", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=None,
+                    help="serve: number of requests (default 200); large: per precision (default 6)")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrivals per second")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serving HBM budget (GB)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM "
                          "byte counters) and exit")
@@ -133,6 +138,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "copies": 2}), flush=True)
         return
+
+    if args.workload in ("serve", "large"):
+        return serve_bench(args)
 
     t0 = time.perf_counter()
     s = make_stack(args.workload)
@@ -209,6 +217,207 @@ def main():
                      "traffic": measured_traffic(), "search_ms": search_ms,
                      "bytes_per_tie": BYTES_PER_TIE_F32},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# --- Serving workloads --------------------------------------------------------
+
+def _survey_request(serve, synth, dev, rid, n_img, h, w, n_speeds, n_angles, seed, k=50,
+                    k_cand=None, **stack_kw):
+    """A survey-shaped request whose inputs are drawn on the device when
+    `make` runs, or ahead of time by `pregenerate(stream)` (then `make` only
+    orders the caller's stream after that generation)."""
+    import torch
+    t = synth.survey_times(n_img)
+    vel = synth.survey_velocities(n_speeds, n_angles)
+    psf = synth.psf_gaussian(1.5, 11)
+    ready = {}
+
+    def generate():
+        ds = synth.device_survey_stack(seed, n_img, h, w, n_speeds, n_angles, dev, k=k,
+                                       **stack_kw)
+        return ds.img, ds.var, ds.mask
+
+    def pregenerate(stream):
+        with torch.cuda.stream(stream):
+            ready["inputs"] = generate()
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        ready["event"] = ev
+
+    def make():
+        if "inputs" not in ready:
+            return generate()
+        torch.cuda.current_stream().wait_event(ready.pop("event"))
+        return ready.pop("inputs")
+    req = serve.Request(rid=rid, shape=(n_img, h, w), t=t, vel=vel, psf=psf, k=k, make=make,
+                        k_cand=k_cand)
+    req.pregenerate = pregenerate
+    return req
+
+
+def _solo(lib, req, lp):
+    """The request run alone, outside the server: planes, search, top-k."""
+    img, var, mask = req.make()
+    n = img.shape[0]
+    kc = req.k_cand or req.k
+    if lp is None:
+        planes = lib.make_psi_phi(img, var, mask, req.psf)
+        cand = lib.search(planes, req.t, req.vel, kc)
+        return lib.topk(cand, req.k, n)
+    planes, src, sc = lib.make_psi_phi(img, var, mask, req.psf, lp=lp)
+    ws = lib.alloc_workspace(n, img.shape[1], img.shape[2], len(req.vel), img.device)
+    cand = lib.search(src, req.t, req.vel, kc, workspace=ws, lp_scale=sc)
+    return lib.topk(cand, req.k, n, rescore=(planes, req.t, req.vel, ws))
+
+
+def _quantiles(lat):
+    a = np.sort(np.asarray(lat))
+    q = lambda f: float(a[min(len(a) - 1, int(math.ceil(f * len(a))) - 1)])
+    return {"p50": q(0.5), "p90": q(0.9), "p99": q(0.99), "max": float(a[-1]),
+            "mean": float(a.mean())}
+
+
+def serve_bench(args):
+    import threading
+    import torch
+    from paper_1901_02492_amd import lib, serve, synth
+    lib.load()
+    dev = torch.device("cuda:0")
+    budget = int(args.budget_gb * 1e9)
+
+    # Warm the kernels with one small request outside any timing.
+    w = _survey_request(serve, synth, dev, -1, 8, 256, 256, 10, 20, seed=1)
+    _solo(lib, w, None)
+    torch.cuda.synchronize()
+
+    if args.workload == "serve":
+        params = synth.serving_requests(args.requests or 200, args.rate)
+        reqs = [_survey_request(serve, synth, dev, p["rid"], p["n_img"], p["h"], p["w"],
+                                p["n_speeds"], p["n_angles"], p["seed"]) for p in params]
+        # Requests checked bit for bit against a solo run afterwards: ten drawn
+        # among those with frames up to 2048^2 (their results stay resident).
+        rng = np.random.default_rng(0)
+        small = [p["rid"] for p in params if p["h"] <= 2048]
+        sample = set(int(x) for x in rng.choice(small, size=min(10, len(small)), replace=False))
+        ex = serve.GpuExecutor(dev, lp=None)
+        srv = serve.Server(ex, budget).start()
+        lat, kept, lock = {}, {}, threading.Lock()
+
+        def on_done(f):
+            try:
+                d = f.result()
+            except Exception as e:          # reported below, never silently dropped
+                with lock:
+                    lat[id(f)] = e
+                return
+            with lock:
+                lat[d.rid] = d.latency
+                if d.rid in sample:
+                    kept[d.rid] = d.result
+            d.result = None
+        # The client draws each request's inputs on its own stream shortly
+        # before the scheduled arrival (a service receives inputs that
+        # already exist), then submits at the arrival time.
+        gen_stream = torch.cuda.Stream(device=dev)
+        lead = 0.3
+
+        def wait_until(target):
+            while True:
+                dt = target - time.perf_counter()
+                if dt <= 0:
+                    return
+                time.sleep(min(dt, 0.005))
+        t_start = time.perf_counter() + 0.5
+        futs = []
+        for p, r in zip(params, reqs):
+            target = t_start + p["arrival"]
+            wait_until(target - lead)
+            r.pregenerate(gen_stream)
+            wait_until(target)
+            r.arrival = target
+            f = srv.submit(r)
+            f.add_done_callback(on_done)
+            futs.append(f)
+        for f in futs:
+            f.exception()
+        t_end = time.perf_counter()
+        srv.stop()
+        errors = [v for v in lat.values() if isinstance(v, Exception)]
+        if errors:
+            raise SystemExit(f"{len(errors)} served requests failed: {errors[0]!r}")
+        tie = sum(r.shape[0] * r.shape[1] * r.shape[2] * len(r.vel) for r in reqs)
+        log(f"served {len(reqs)} requests in {t_end - t_start:.1f} s, peak "
+            f"{srv.peak_bytes / 1e9:.1f} GB, batches {len(srv.batches)}")
+        same = 0
+        for rid in sorted(sample):
+            solo = _solo(lib, reqs[rid], None)
+            same += all(torch.equal(a, b) for a, b in zip(kept[rid], solo))
+            del solo
+        kept.clear()
+        lq = _quantiles([lat[r.rid] for r in reqs])
+        out = {
+            "metric": "trajectory-image evals/s", "value": tie / (t_end - t_start),
+            "unit": "trajectory-image evals/s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
+            "ms_per_step": lq["mean"] * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"serving: {len(reqs)} requests, Poisson {args.rate:g}/s, "
+                                   "N 8-20, frames 1024^2/2048^2/4096^2, V 200-2000, K=50, "
+                                   f"budget {args.budget_gb:g} GB",
+                       "tie_total": tie, "wall_s": t_end - t_start},
+            "latency_s": lq,
+            "server": {"peak_gb": srv.peak_bytes / 1e9, "launches": len(srv.batches),
+                       "max_batch": max(srv.batches)},
+            "alone_vs_mix": {"checked": len(sample), "bitwise_equal": same},
+        }
+        print(json.dumps(out), flush=True)
+        return
+
+    # Large stacks under sustained load: a closed loop keeping two requests
+    # outstanding, 16-bit search with FP32 re-score, then plain FP32.
+    n_req = args.requests or 6
+    res = {}
+    for lp in ("f16", None):
+        reqs = [_survey_request(serve, synth, dev, q, 25, 4096, 4096, 50, 80,
+                                seed=synth.SEED_BASE + 4000 + q, src_per_16m=300.0,
+                                snr=(4.0, 15.0)) for q in range(n_req)]
+        ex = serve.GpuExecutor(dev, lp=lp)
+        srv = serve.Server(ex, budget).start()
+        lat = []
+        t0 = time.perf_counter()
+        pending = [srv.submit(r) for r in reqs[:2]]
+        nxt = 2
+        while pending:
+            f = pending.pop(0)
+            d = f.result()
+            lat.append(d.latency)
+            d.result = None
+            if nxt < n_req:
+                pending.append(srv.submit(reqs[nxt]))
+                nxt += 1
+        t1 = time.perf_counter()
+        srv.stop()
+        tie = sum(r.shape[0] * r.shape[1] * r.shape[2] * len(r.vel) for r in reqs)
+        res[lp or "f32"] = {"value": tie / (t1 - t0), "latency_s": _quantiles(lat),
+                            "wall_s": t1 - t0}
+        log(f"large {lp or 'f32'}: {tie / (t1 - t0):.3e} TIE/s")
+    r16 = res["f16"]
+    out = {
+        "metric": "trajectory-image evals/s", "value": r16["value"],
+        "unit": "trajectory-image evals/s", "n_gpus": 1, "steps": n_req, "warmup": 1,
+        "ms_per_step": r16["latency_s"]["mean"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f16 planes, f32 accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"closed loop, 2 outstanding, {n_req} requests of 25x4096x4096, "
+                               "4000 velocities (50 speeds x 80 angles), K=50, FP16 search + "
+                               "FP32 re-score", "tie_per_request": 25 * 4096 * 4096 * 4000},
+        "latency_s": r16["latency_s"],
+        "roofline": {"bound": "hbm", "kernel": "whole request", "achieved":
+                     4.0 * r16["value"] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": 4.0 * r16["value"] / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_tie": 4.0},
+        "f32_same_requests": res["f32"],
     }
     print(json.dumps(out), flush=True)
 

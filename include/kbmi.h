@@ -23,6 +23,9 @@
  *   - Device pointers are HIP device memory owned by the caller.  Host
  *     pointers (marked "host") are read before the call returns.  The library
  *     allocates no device memory and keeps no pointer after a call returns.
+ *     Tables that a call sends to its workspace go through pinned host
+ *     buffers the library keeps per device (at most 32, reused once the copy
+ *     out of them has completed), so calls do not wait for their stream.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
  *     enqueued asynchronously on it; the caller keeps every device buffer
  *     alive until the stream has passed the work.  Calls on different streams
@@ -150,9 +153,9 @@ size_t kb_search_workspace_bytes(int64_t n_img, int64_t h, int64_t w, int64_t n_
  *              order (kb_topk accepts them in any order).
  *   workspace  device, >= kb_search_workspace_bytes(n_img, h, w, n_vel)
  *              bytes, 256-byte aligned; overwritten.
- * Limits: n_img <= 32767, n_vel <= 65535, w <= 2^27, h <= 2^31 - 1.
- * The displacement table is copied host-to-device on `stream`; from pageable
- * memory that copy may wait for earlier work on the stream.
+ * Limits: n_img <= 32767, n_vel <= 65535, w <= 2^27, h <= 2^30.
+ * The displacement table is copied host-to-device on `stream`
+ * (asynchronously, through the library's pinned staging buffers).
  * Errors: KB_EINVAL for bad sizes, pointers or times; KB_ENOMEM for a short
  * workspace; KB_EUNSUPPORTED for k_cand > KB_MAX_KCAND.
  */
@@ -222,7 +225,7 @@ size_t kb_search_batch_workspace_bytes(const kb_job *jobs, int64_t n_jobs);
  *   workspace  device, >= kb_search_batch_workspace_bytes(jobs, n_jobs),
  *              256-byte aligned; overwritten.
  * The displacement tables and job descriptors are copied host-to-device on
- * `stream` and the call waits for that copy.
+ * `stream` (asynchronously, through the library's pinned staging buffers).
  * Errors: as kb_search for any job (the message names the job index), plus
  * KB_EINVAL for n_jobs out of range or more workgroups than one launch holds.
  */

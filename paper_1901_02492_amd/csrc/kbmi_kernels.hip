@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "kbmi_device.h"
@@ -370,9 +371,77 @@ kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
     return KB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Host staging of table uploads.  Each upload is copied into a pinned host
+// buffer, sent with an asynchronous copy on the caller's stream, and followed
+// by an event; a buffer is reused once its event has completed.  Calls thus
+// return without waiting for their stream.  Buffers are kept per device (at
+// most kStagingPerDevice; beyond that a call waits for one of them) until the
+// process ends.
+// ---------------------------------------------------------------------------
+struct StagingBuffer {
+    void *host;
+    size_t cap;
+    hipEvent_t done;
+    int device;
+};
+constexpr int kStagingPerDevice = 32;
+std::mutex g_staging_mu;
+std::vector<StagingBuffer *> g_staging;
+
+kb_status staged_copy(void *dst, const void *src, size_t bytes, hipStream_t stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(KB_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(g_staging_mu);
+    StagingBuffer *b = nullptr;
+    int owned = 0;
+    for (StagingBuffer *x : g_staging) {
+        if (x->device != dev) continue;
+        ++owned;
+        if (!b && x->cap >= bytes && hipEventQuery(x->done) == hipSuccess) b = x;
+    }
+    if (!b && owned >= kStagingPerDevice) {
+        // Wait for this device's first buffer and resize it if needed.
+        for (StagingBuffer *x : g_staging)
+            if (x->device == dev) {
+                b = x;
+                break;
+            }
+        e = hipEventSynchronize(b->done);
+        if (e == hipSuccess && b->cap < bytes) {
+            e = hipHostFree(b->host);
+            b->host = nullptr;
+            b->cap = 0;
+            if (e == hipSuccess) e = hipHostMalloc(&b->host, bytes, hipHostMallocDefault);
+            if (e == hipSuccess) b->cap = bytes;
+        }
+        if (e != hipSuccess)
+            return fail(KB_EDEVICE, "staging buffer: %s", hipGetErrorString(e));
+    }
+    if (!b) {
+        b = new StagingBuffer{nullptr, 0, nullptr, dev};
+        const size_t cap = std::max(bytes, static_cast<size_t>(1) << 16);
+        e = hipHostMalloc(&b->host, cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (b->host) (void)hipHostFree(b->host);
+            delete b;
+            return fail(KB_ENOMEM, "pinned staging buffer of %zu bytes: %s", cap,
+                        hipGetErrorString(e));
+        }
+        b->cap = cap;
+        g_staging.push_back(b);
+    }
+    std::memcpy(b->host, src, bytes);
+    e = hipMemcpyAsync(dst, b->host, bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(b->done, stream);
+    if (e != hipSuccess) return fail(KB_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
+    return KB_OK;
+}
+
 // Copy the gather table (for planes of `pix_bytes` bytes per pair) and the
-// visiting order into the workspace.  The host copies are pageable and
-// temporary, so the call waits until they have reached the device.
+// visiting order into the workspace, asynchronously on `stream`.
 kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                        int64_t h, int64_t w, int64_t pix_bytes, void *workspace,
                        hipStream_t stream, bool visiting_order = true) {
@@ -382,12 +451,7 @@ kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_
                  reinterpret_cast<GatherEntry *>(host.data()),
                  reinterpret_cast<int32_t *>(host.data() + tb));
     // The order follows the (256-byte rounded) table directly in the workspace.
-    hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice,
-                                  stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess)
-        return fail(KB_EDEVICE, "displacement table upload failed: %s", hipGetErrorString(e));
-    return KB_OK;
+    return staged_copy(workspace, host.data(), host.size(), stream);
 }
 
 }  // namespace
@@ -664,10 +728,8 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
         block_begin += d.nseg * d.h;
     }
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess)
-        return fail(KB_EDEVICE, "batch upload failed: %s", hipGetErrorString(e));
+    kb_status up = staged_copy(ws, host.data(), host.size(), s);
+    if (up != KB_OK) return up;
     if (dtype != KB_F32) {
         for (int64_t q = 0; q < n_jobs; ++q) {
             const int stride = (int)table_stride(jobs[q].n_img);

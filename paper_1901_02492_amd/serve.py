@@ -7,11 +7,13 @@ arrive while others run.  The scheduler
     HBM budget (a request larger than the whole budget fails at once);
   * prepares each admitted request on the device (inputs, likelihood planes,
     candidate and result buffers) as soon as it is admitted;
-  * launches the searches of everything prepared since the last launch as ONE
-    batched search (kb_search_batch: one persistent launch over the tiles of
-    all those stacks) followed by each stack's final top-k, keeping up to
-    `max_inflight` such batches queued on the device so it never idles
-    between them;
+  * launches prepared requests in arrival order, packing consecutive ones
+    into ONE batched search (kb_search_batch: one persistent launch over the
+    tiles of all those stacks) while the batch's work stays within
+    `batch_work` trajectory-image evaluations (a larger request runs alone,
+    so small stacks never wait for a large one that shares their launch),
+    each followed by its stacks' final top-k, and keeps up to `max_inflight`
+    batches queued on the device so it never idles between them;
   * resolves each request's future when its results are ready and frees its
     memory, which admits the next requests.
 
@@ -61,10 +63,11 @@ class Done:
 
 class Server:
     def __init__(self, executor, budget_bytes: int, max_batch: int = 64,
-                 max_inflight: int = 2, poll_s: float = 2e-4):
+                 max_inflight: int = 2, poll_s: float = 2e-4, batch_work: float = 2e10):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
+        self.batch_work = batch_work
         self.max_inflight = max_inflight
         self.poll_s = poll_s
         self._lock = threading.Condition()
@@ -144,9 +147,25 @@ class Server:
             self._in_use -= n
             self._lock.notify()
 
+    @staticmethod
+    def work(req: Request) -> int:
+        """Trajectory-image evaluations of a request: N * H * W * V."""
+        n, h, w = req.shape
+        return int(n) * int(h) * int(w) * len(req.vel)
+
+    def _next_batch(self):
+        take, total = 0, 0
+        while take < len(self._ready) and take < self.max_batch:
+            wk = self.work(self._ready[take][0])
+            if take and total + wk > self.batch_work:
+                break
+            take, total = take + 1, total + wk
+        batch, self._ready = self._ready[:take], self._ready[take:]
+        return batch
+
     def _launch(self):
         while self._ready and len(self._inflight) < self.max_inflight:
-            batch, self._ready = self._ready[:self.max_batch], self._ready[self.max_batch:]
+            batch = self._next_batch()
             try:
                 token = self.ex.launch([h for _, _, h, _ in batch])
             except Exception as e:
@@ -208,8 +227,10 @@ def footprint_bytes(n_img, h, w, n_vel, k, k_cand, lp=None) -> int:
 
 
 class GpuExecutor:
-    """Runs requests with libkbmi on one HIP device.  Batches go to the
-    device streams round-robin; results stay on the device."""
+    """Runs requests with libkbmi on one HIP device.  Inputs and planes are
+    prepared on a stream of their own; batches go to the search streams
+    round-robin, each waiting for its requests' preparation; results stay on
+    the device."""
 
     def __init__(self, device="cuda:0", lp=None, streams=2):
         import torch
@@ -217,6 +238,7 @@ class GpuExecutor:
         self.torch, self.lib = torch, lib
         self.dev = torch.device(device)
         self.lp = lp
+        self.prep_stream = torch.cuda.Stream(device=self.dev)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
         self._next = 0
 
@@ -227,7 +249,7 @@ class GpuExecutor:
 
     def prepare(self, req: Request):
         torch, lib = self.torch, self.lib
-        s = self.streams[self._next % len(self.streams)]
+        s = self.prep_stream
         with torch.cuda.stream(s):
             img, var, mask = req.make()
             n, h, w = img.shape
@@ -279,12 +301,13 @@ class GpuExecutor:
 
     def release(self, handle):
         # Tensors return to torch's caching allocator once unreferenced; make
-        # the allocator aware of the stream that used them.
+        # the allocator aware of the stream that used them (a request whose
+        # batch never launched only ran on the preparation stream).
         s = handle["stream"]
         for key in ("img", "var", "mask", "planes", "src", "scale", "ws"):
             t = handle.get(key)
             if t is not None:
                 t.record_stream(s)
-        for t in handle["cand"]:
+        for t in (*handle["cand"], *handle["out"]):
             t.record_stream(s)
         handle.clear()

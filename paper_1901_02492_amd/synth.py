@@ -246,3 +246,130 @@ def random_stack(seed: int, n: int, h: int, w: int, n_vel: int, k: int,
         src.append((x0, y0, vx, vy, 20.0))
     return Stack(img, var, mask, t, psf_gaussian(psf_sigma, psf_size), vel, k,
                  np.array(src, dtype=np.float64).reshape(-1, 5), name=f"random{seed}")
+
+
+# ---------------------------------------------------------------------------
+# Device-side generation (serving workloads): the survey recipe drawn with the
+# device's own random generator, so that a request's inputs appear in
+# milliseconds.  Same seed, shape and device give the same bytes.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DeviceStack:
+    img: "object"            # torch float32 [N][H][W] on the device
+    var: "object"            # torch float32 [N][H][W]
+    mask: "object"           # torch uint8 [N][H][W]
+    t: np.ndarray
+    psf: np.ndarray
+    vel: np.ndarray
+    k: int
+    sources: np.ndarray
+    name: str = ""
+
+    @property
+    def tie(self) -> int:
+        n, h, w = self.img.shape
+        return int(n) * int(h) * int(w) * int(self.vel.shape[0])
+
+
+def survey_times(n_img: int, epochs: int = 5) -> np.ndarray:
+    """Observation times of a survey-shaped stack: `epochs` visits 0.06 d apart
+    per night, consecutive nights, n_img images in total."""
+    return np.array([i // epochs + 0.06 * (i % epochs) for i in range(n_img)], dtype=np.float64)
+
+
+def survey_velocities(n_speeds: int, n_angles: int) -> np.ndarray:
+    """Speed x angle grid of the survey workloads: speeds linspace(80, 400) px/d,
+    angles linspace(-0.5, 0.5) rad (Sec. 3.1's linearly spaced grid)."""
+    return velocity_grid_polar(np.linspace(80.0, 400.0, n_speeds), np.linspace(-0.5, 0.5, n_angles))
+
+
+def serving_requests(n: int = 200, rate: float = 4.0, seed: int = SEED_BASE + 3000):
+    """Request stream of the serving workload: Poisson arrivals at `rate` per
+    second (seeded exponential gaps, the first at 0), N uniform in 8..20, frames
+    1024^2, 2048^2 or 4096^2, V uniform in [200, 2000] rounded to a multiple of
+    20 and laid out as V/20 speeds x 20 angles.  Each entry carries the seed of
+    its own stack."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for q in range(n):
+        n_img = int(rng.integers(8, 21))
+        side = int(rng.choice([1024, 2048, 4096]))
+        v = int(round(rng.uniform(200.0, 2000.0) / 20.0)) * 20
+        out.append(dict(rid=q, arrival=float(arrivals[q]), n_img=n_img, h=side, w=side,
+                        n_speeds=v // 20, n_angles=20, seed=seed + 1 + q))
+    return out
+
+
+def device_survey_stack(seed: int, n_img: int, h: int, w: int, n_speeds: int, n_angles: int,
+                        device, k: int = 50, src_per_16m: float = 100.0, snr=(5.0, 20.0),
+                        mask_frac: float = 0.01, psf_sigma: float = 1.5,
+                        psf_size: int = 11) -> DeviceStack:
+    """A survey-shaped stack generated on `device`: survey times, noise sigma
+    1 + 0.2 sin sin (per-image phases) with var = sigma^2, random masks,
+    sources at speeds 80-400 px/d within +-0.5 rad (src_per_16m per 4096^2
+    pixels, flux for the drawn signal-to-noise over the epochs in frame) and a
+    speed x angle grid over the same ranges."""
+    import torch
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    t = survey_times(n_img)
+    ph = rng.random((n_img, 2))
+    xs = torch.arange(w, device=device, dtype=torch.float64) / w
+    ys = torch.arange(h, device=device, dtype=torch.float64) / h
+    sig = torch.empty((n_img, h, w), device=device, dtype=torch.float32)
+    for i in range(n_img):
+        sx = torch.sin(2 * math.pi * (xs + float(ph[i, 0])))
+        sy = torch.sin(2 * math.pi * (ys + float(ph[i, 1])))
+        sig[i] = (1.0 + 0.2 * torch.outer(sy, sx)).to(torch.float32)
+    img = torch.randn((n_img, h, w), generator=gen, device=device, dtype=torch.float32)
+    img.mul_(sig)
+    var = sig.square_()
+    mask = (torch.rand((n_img, h, w), generator=gen, device=device) < mask_frac).to(torch.uint8)
+    psf = psf_gaussian(psf_sigma, psf_size)
+    s2 = float(np.sum(psf.astype(np.float64) ** 2))
+    n_src = int(round(src_per_16m * h * w / float(4096 * 4096)))
+    srcs = []
+    r = int(math.ceil(5.0 * psf_sigma))
+    stamps_idx, stamps_val = [], []
+    for _ in range(n_src):
+        x0, y0 = rng.uniform(0, w), rng.uniform(0, h)
+        sp, an = rng.uniform(80.0, 400.0), rng.uniform(-0.5, 0.5)
+        target = rng.uniform(*snr)
+        vx, vy = sp * math.cos(an), sp * math.sin(an)
+        inv = 0.0
+        for i in range(n_img):
+            cx, cy = x0 + vx * (t[i] - t[0]), y0 + vy * (t[i] - t[0])
+            if 0 <= cx < w and 0 <= cy < h:
+                s = (1.0 + 0.2 * math.sin(2 * math.pi * (int(cx) / w + ph[i, 0])) *
+                     math.sin(2 * math.pi * (int(cy) / h + ph[i, 1])))
+                inv += s2 / (s * s)
+        flux = target / math.sqrt(inv) if inv > 0 else 0.0
+        for i in range(n_img):
+            cx, cy = x0 + vx * (t[i] - t[0]), y0 + vy * (t[i] - t[0])
+            xa, xb = max(int(math.floor(cx)) - r, 0), min(int(math.floor(cx)) + r + 1, w)
+            ya, yb = max(int(math.floor(cy)) - r, 0), min(int(math.floor(cy)) + r + 1, h)
+            if xa >= xb or ya >= yb:
+                continue
+            gx = (ndtr((np.arange(xa, xb) + 0.5 - cx) / psf_sigma) -
+                  ndtr((np.arange(xa, xb) - 0.5 - cx) / psf_sigma))
+            gy = (ndtr((np.arange(ya, yb) + 0.5 - cy) / psf_sigma) -
+                  ndtr((np.arange(ya, yb) - 0.5 - cy) / psf_sigma))
+            yy, xx = np.meshgrid(np.arange(ya, yb), np.arange(xa, xb), indexing="ij")
+            stamps_idx.append(((i * h + yy) * w + xx).ravel())
+            stamps_val.append((flux * np.outer(gy, gx)).ravel())
+        srcs.append((x0, y0, vx, vy, flux))
+    if stamps_idx:
+        # Overlapping stamps are summed on the host (fixed order), so that every
+        # pixel is written once and the bytes do not depend on atomics.
+        uidx, inv = np.unique(np.concatenate(stamps_idx), return_inverse=True)
+        uval = np.bincount(inv, weights=np.concatenate(stamps_val)).astype(np.float32)
+        idx = torch.from_numpy(uidx).to(device)
+        flat = img.view(-1)
+        flat[idx] = flat[idx] + torch.from_numpy(uval).to(device)
+    vel = survey_velocities(n_speeds, n_angles)
+    return DeviceStack(img, var, mask, t, psf, vel, k, np.array(srcs, dtype=np.float64).reshape(-1, 5),
+                       name=f"{n_img}x{h}x{w}, {n_speeds * n_angles} velocities, K={k}")

@@ -54,8 +54,8 @@ class FakeExecutor:
             self.live -= self.footprint(h["req"])
 
 
-def _req(rid, shape=(2, 4, 4), arrival=0.0):
-    return Request(rid=rid, shape=shape, t=None, vel=[0] * 10, psf=None, k=1, make=None,
+def _req(rid, shape=(2, 4, 4), arrival=0.0, n_vel=10):
+    return Request(rid=rid, shape=shape, t=None, vel=[0] * n_vel, psf=None, k=1, make=None,
                    arrival=arrival)
 
 
@@ -81,6 +81,21 @@ def test_requests_are_batched_when_they_queue_up():
         f.result(timeout=10)
     srv.stop()
     assert max(srv.batches) == 8 and sum(srv.batches) == 16
+
+
+def test_batches_respect_the_work_cap():
+    # Work per request: n * h * w * V.  Small ones (320) pack up to the cap of
+    # 1000; a large one (4000) runs alone; order stays FIFO.
+    ex = FakeExecutor(cost_s=0.005)
+    srv = Server(ex, budget_bytes=10 ** 9, max_inflight=1, batch_work=1000)
+    sizes = [(2, 4, 4)] * 3 + [(10, 20, 2)] + [(2, 4, 4)] * 4
+    futs = [srv.submit(_req(i, shape=sh)) for i, sh in enumerate(sizes)]
+    srv.start()
+    for f in futs:
+        f.result(timeout=10)
+    srv.stop()
+    assert srv.batches == [3, 1, 3, 1]
+    assert ex.order == list(range(len(sizes)))
 
 
 def test_oversized_request_fails_alone():
