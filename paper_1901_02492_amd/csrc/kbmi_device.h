@@ -20,6 +20,15 @@
 #ifndef KBMI_PREFETCH
 #define KBMI_PREFETCH 1         // single-stack search: fetch the next table row early
 #endif
+#ifndef KBMI_SUPER_W
+#define KBMI_SUPER_W 2          // tiles per XCD strip in the super-strip order (0: off)
+#endif
+#ifndef KBMI_PERSIST_BS
+#define KBMI_PERSIST_BS 0       // tiles per block row in the persistent order (0: off)
+#endif
+#ifndef KBMI_PERSIST_SPIN
+#define KBMI_PERSIST_SPIN 4000  // bound of a wave's wait at a generation boundary
+#endif
 
 // List lengths compiled for the search: every even length up to KB_MAX_KCAND
 // (each slot costs registers and compare-and-swap work on every insertion).
@@ -44,6 +53,7 @@ struct StackView {
     float *cand_nu, *cand_alpha;
     int32_t *cand_vel;
     int16_t *cand_nobs;
+    uint32_t *sync;            // per-XCD generation counters of the persistent search
 };
 
 // One stack of a batched search, as the batch kernel reads it from device memory.
@@ -195,14 +205,59 @@ __device__ inline void strip_tile(int t, int nseg, int h, int strip, int &row, i
     }
 }
 
+// Super-strip order (used when nseg is a multiple of 8 * sw): the frame is
+// cut into vertical super-strips 8 * sw tiles wide; within one, XCD x owns
+// the sw-tile strip x and walks it top to bottom.  The eight XCDs then sweep
+// down the same super-strip together, so the rows that later start rows
+// gather again (every velocity reaches up to the longest displacement) stay
+// within a window the memory-side cache can hold.
+__device__ inline void superstrip_tile(int b, int h, int sw, int &row, int &seg) {
+    const int xcd = b & 7, m = b >> 3;
+    const int per = sw * h;
+    const int ss = m / per;
+    const int rem = m - ss * per;
+    row = rem / sw;
+    seg = (ss * 8 + xcd) * sw + (rem - row * sw);
+}
+
 struct TileMap {
     int nseg;     // tiles per row
     int h;        // rows
     int strip;    // tiles per strip
     int nblocks;  // nseg * h
+    int sw;       // > 0: super-strip order with sw-tile strips per XCD
 
     __device__ inline void map(int b, int &row, int &seg) const {
-        strip_tile(xcd_remap(b, nblocks), nseg, h, strip, row, seg);
+        if (sw > 0) superstrip_tile(b, h, sw, row, seg);
+        else strip_tile(xcd_remap(b, nblocks), nseg, h, strip, row, seg);
+    }
+};
+
+// Persistent order: the grid is exactly the number of workgroups the GPU
+// holds at once, and workgroup w processes one tile per generation.  In a
+// generation, XCD x (workgroups w = 8k + x, dispatched round-robin over the
+// XCDs) covers one block of bs x brows tiles (k -> row k / bs, seg k % bs),
+// the eight XCDs take eight side-by-side blocks, and generations move down
+// the frame, then to the next eight block columns.  Waves that start a
+// generation together walk the velocities roughly in step, so one velocity's
+// gathers find the rows the block read for the previous ones still in L2.
+// Every in-frame tile belongs to exactly one (generation, workgroup); slots
+// past the frame's edge are skipped.
+struct PersistMap {
+    int nseg, h;
+    int bs, brows;     // block: bs tiles wide, brows rows tall (bs * brows = grid / 8)
+    int nbc, nbr;      // blocks per row of blocks, rows of blocks
+    int generations;   // ceil(nbc / 8) * nbr
+    int spin;          // bound of a wave's wait at a generation boundary (0: no wait)
+    __device__ inline bool map(int gen, int w, int &row, int &seg) const {
+        const int xcd = w & 7, k = w >> 3;
+        const int sc = gen / nbr;
+        const int br = gen - sc * nbr;
+        const int bc = sc * 8 + xcd;
+        const int q = k / bs;
+        row = br * brows + q;
+        seg = bc * bs + (k - q * bs);
+        return bc < nbc && row < h && seg < nseg;
     }
 };
 
@@ -499,6 +554,42 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
                                                      disp_stride,
                                  vel_index, n_vel, k_cand, row, seg, cand_nu, cand_alpha,
                                  cand_vel, cand_nobs);
+}
+
+// The single-stack search in the persistent order (large frames).
+template <int KM, int NB, int PB, int FMT>
+__global__ __launch_bounds__(64, 2) void search_persistent_kernel(
+    const void *__restrict__ planes, const float2 *__restrict__ inv_scale, int n_img, int h,
+    int w, const GatherEntry *__restrict__ disp, int disp_stride,
+    const int32_t *__restrict__ vel_index, int n_vel, int k_cand, PersistMap pm,
+    float *__restrict__ cand_nu, float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
+    int16_t *__restrict__ cand_nobs, uint32_t *sync) {
+    __shared__ uint32_t lds[search_lds_words<KM, PB>()];
+    uint32_t *xcd_count = sync + (blockIdx.x & 7);
+    const uint32_t per_xcd = gridDim.x >> 3;
+    for (int gen = 0; gen < pm.generations; ++gen) {
+        int row, seg;
+        if (pm.map(gen, (int)blockIdx.x, row, seg))
+            search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(
+                lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel,
+                k_cand, row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
+        // Generation boundary: wait (a bounded time) until every workgroup of
+        // this XCD has finished the generation, so its waves start the next
+        // block together.  The wait only shapes timing; no result depends on it.
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(xcd_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (uint32_t)(gen + 1) * per_xcd;
+        for (int i = 0; i < pm.spin; ++i) {
+            if (__hip_atomic_load(xcd_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                target)
+                break;
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+}
+
+__global__ void zero_words_kernel(uint32_t *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------

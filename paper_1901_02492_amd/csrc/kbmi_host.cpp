@@ -139,7 +139,8 @@ WorkspaceLayout workspace_layout(int64_t n_img, int64_t h, int64_t w, int64_t n_
     l.table = 0;
     l.order = l.table + table_bytes(n_img, n_vel);
     l.inv_scale = l.order + order_bytes(n_vel);
-    l.total = l.inv_scale + align256(static_cast<size_t>(table_stride(n_img)) * 8);
+    l.sync = l.inv_scale + align256(static_cast<size_t>(table_stride(n_img)) * 8);
+    l.total = l.sync + 256;
     (void)h;
     (void)w;
     return l;

@@ -58,10 +58,11 @@ void gather_table(const double *t, int64_t n_img, const double *vel, int64_t n_v
                   int64_t w, int64_t pix_bytes, bool visiting_order, GatherEntry *table,
                   int32_t *order);
 // Whole workspace of kb_search / kb_topk (byte offsets, 256-byte aligned): the
-// table, the visiting order and the 16-bit search's per-image inverse scales
-// (float2 [table_stride]).
+// table, the visiting order, the 16-bit search's per-image inverse scales
+// (float2 [table_stride]) and the persistent search's per-XCD generation
+// counters (uint32 [8], zeroed by each launch).
 struct WorkspaceLayout {
-    size_t table, order, inv_scale, total;
+    size_t table, order, inv_scale, sync, total;
 };
 WorkspaceLayout workspace_layout(int64_t n_img, int64_t h, int64_t w, int64_t n_vel);
 

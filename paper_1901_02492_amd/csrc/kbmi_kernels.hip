@@ -561,6 +561,7 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     sv.cand_alpha = cand_alpha;
     sv.cand_vel = cand_vel;
     sv.cand_nobs = cand_nobs;
+    sv.sync = reinterpret_cast<uint32_t *>(wsb + lay.sync);
     if (dtype != KB_F32) {
         const int stride = (int)table_stride(n_img);
         hipLaunchKernelGGL(inv_scale_kernel, dim3((stride + 63) / 64), dim3(64), 0, s, lp_scale,

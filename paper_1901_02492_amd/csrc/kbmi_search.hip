@@ -26,13 +26,59 @@ TileMap tile_map(int w, int h) {
     tm.h = h;
     tm.strip = tm.nseg < KBMI_STRIP_TILES ? tm.nseg : KBMI_STRIP_TILES;
     tm.nblocks = tm.nseg * h;
+    tm.sw = (KBMI_SUPER_W > 0 && tm.nseg % (8 * KBMI_SUPER_W) == 0) ? KBMI_SUPER_W : 0;
     return tm;
+}
+
+// Workgroups of `kernel` the device holds at once (0 if unknown), cached per
+// device and kernel.
+template <typename K>
+int resident_workgroups(K kernel) {
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess)
+            return 0;
+        cached[dev] = per_cu * cus;
+    }
+    return cached[dev];
 }
 
 template <int KM, int NB>
 kb_status launch_one(const StackView &v, hipStream_t s) {
     constexpr int PB = KBMI_QUEUE;
     static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
+    if (KBMI_PERSIST_BS > 0) {
+        auto kernel = search_persistent_kernel<KM, NB, PB, KBMI_FMT>;
+        const int grid = resident_workgroups(kernel);
+        const int nseg = (v.w + 63) / 64;
+        const int per_xcd = grid / 8;
+        // Worth it only when the frame holds several generations of blocks.
+        if (grid >= 8 && grid % 8 == 0 && per_xcd % KBMI_PERSIST_BS == 0 &&
+            (int64_t)nseg * v.h >= 4 * (int64_t)grid) {
+            PersistMap pm;
+            pm.nseg = nseg;
+            pm.h = v.h;
+            pm.bs = KBMI_PERSIST_BS;
+            pm.brows = per_xcd / KBMI_PERSIST_BS;
+            pm.nbc = (nseg + pm.bs - 1) / pm.bs;
+            pm.nbr = (v.h + pm.brows - 1) / pm.brows;
+            pm.generations = (pm.nbc + 7) / 8 * pm.nbr;
+            pm.spin = KBMI_PERSIST_SPIN;
+            hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, v.sync, 8);
+            kb_status st = launch_status("zero_words_kernel");
+            if (st != KB_OK) return st;
+            hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, v.planes, v.inv_scale,
+                               v.n_img, v.h, v.w, v.disp, v.disp_stride, v.vel_index, v.n_vel,
+                               v.k_cand, pm, v.cand_nu, v.cand_alpha, v.cand_vel, v.cand_nobs,
+                               v.sync);
+            return launch_status("search_persistent_kernel");
+        }
+    }
     const TileMap tm = tile_map(v.w, v.h);
     hipLaunchKernelGGL((search_kernel<KM, NB, PB, KBMI_FMT>), dim3(tm.nblocks), dim3(64), 0, s,
                        v.planes, v.inv_scale, v.n_img, v.h, v.w, v.disp, v.disp_stride,

@@ -80,6 +80,15 @@ def test_random_stacks(torch_dev, case):
     _full_check(torch_dev, s, k_cand=kc, k=k)
 
 
+def test_persistent_order_ragged_frame(torch_dev):
+    """A frame large enough for the persistent tile order (several generations
+    of blocks at K' = 50) with a ragged width and height, so that blocks
+    overhang the right and bottom edges: every start pixel is compared with
+    the oracle."""
+    s = synth.random_stack(21, n=8, h=520, w=1000, n_vel=60, k=50, psf_size=5, vmax=60.0)
+    _full_check(torch_dev, s)
+
+
 def test_fully_masked_image_and_bad_pixels(torch_dev):
     s = synth.random_stack(11, n=4, h=30, w=70, n_vel=10, k=4, psf_size=3)
     s.mask[2] = 1
