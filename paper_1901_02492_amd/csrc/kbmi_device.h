@@ -7,8 +7,10 @@
 
 #include <cmath>
 #include <cstdint>
+#include <utility>
 
 #include "kbmi_internal.h"
+#include "kbmi_merge_network.h"
 
 // Launch-shape defaults (compile-time tunables).
 #ifndef KBMI_STRIP_TILES
@@ -24,7 +26,7 @@
 #define KBMI_SUPER_W 2          // tiles per XCD strip in the super-strip order (0: off)
 #endif
 #ifndef KBMI_PERSIST_BS
-#define KBMI_PERSIST_BS 0       // tiles per block row in the persistent order (0: off)
+#define KBMI_PERSIST_BS 2       // float32 planes: tiles per block row in the persistent order (0: off)
 #endif
 #ifndef KBMI_PERSIST_SPIN
 #define KBMI_PERSIST_SPIN 4000  // bound of a wave's wait at a generation boundary
@@ -157,6 +159,57 @@ __device__ inline void key_exchange(uint64_t &k, uint64_t &n) {
         : "v"(__builtin_bit_cast(double, n)));
     k = __builtin_bit_cast(uint64_t, kd);
     n = __builtin_bit_cast(uint64_t, t);
+}
+
+// k <- max(k, n) as keys.
+__device__ inline uint64_t key_max(uint64_t k, uint64_t n) {
+    double kd = __builtin_bit_cast(double, k);
+    asm("v_max_f64 %0, %0, %1" : "+v"(kd) : "v"(__builtin_bit_cast(double, n)));
+    return __builtin_bit_cast(uint64_t, kd);
+}
+
+// Merging a batch of 16 queued candidates into the descending list of KM
+// (registers 0..KM-1 of r/ra; the batch in KM..KM+15) with the generated
+// comparator network, keeping the best KM.  Alpha follows its key.
+template <int KIND, int A, int B, int N>
+__device__ __forceinline__ void net_op(uint64_t (&r)[N], float (&ra)[N]) {
+    const bool c = r[B] > r[A];
+    if constexpr (KIND == 0) {
+        key_exchange(r[A], r[B]);
+        const float t = c ? ra[B] : ra[A];
+        ra[B] = c ? ra[A] : ra[B];
+        ra[A] = t;
+        // Materialise both outputs here (no code): otherwise the alpha
+        // selects sink to their uses and every compare result stays live.
+        asm volatile("" : "+v"(r[A]), "+v"(r[B]), "+v"(ra[A]), "+v"(ra[B]));
+    } else {
+        r[A] = key_max(r[A], r[B]);
+        ra[A] = c ? ra[B] : ra[A];
+        asm volatile("" : "+v"(r[A]), "+v"(ra[A]));
+    }
+}
+template <int KM, int N, size_t... I>
+__device__ __forceinline__ void net_run(uint64_t (&r)[N], float (&ra)[N],
+                                        std::index_sequence<I...>) {
+    // Applied in program order: interleaving the network's independent
+    // exchanges would only lengthen live ranges past the register file.
+    ((net_op<MergeNetwork<KM>::ops[I].kind, MergeNetwork<KM>::ops[I].a,
+             MergeNetwork<KM>::ops[I].b>(r, ra),
+      __builtin_amdgcn_sched_barrier(0)),
+     ...);
+}
+template <int KM, int N, size_t... S>
+__device__ __forceinline__ void net_place(uint64_t (&r)[N], float (&ra)[N],
+                                          std::index_sequence<S...>) {
+    // List slot s takes register perm[s] (fixed swaps of the network).
+    const uint64_t k[KM] = {r[MergeNetwork<KM>::perm[S]]...};
+    const float a[KM] = {ra[MergeNetwork<KM>::perm[S]]...};
+    ((r[S] = k[S], ra[S] = a[S]), ...);
+}
+template <int KM, int N>
+__device__ __forceinline__ void net_merge(uint64_t (&r)[N], float (&ra)[N]) {
+    net_run<KM>(r, ra, std::make_index_sequence<MergeNetwork<KM>::n_ops>());
+    net_place<KM>(r, ra, std::make_index_sequence<KM>());
 }
 
 // Scores of one trajectory (Sec. 2.1.5): nu = Psi / sqrt(Phi) and
@@ -325,10 +378,14 @@ __device__ __forceinline__ void search_tile(
     const uint32_t row_bytes = (uint32_t)w * kPix;
     const size_t img_bytes = (size_t)h * (size_t)w * kPix;
 
-    uint64_t key[KM];
-    float al[KM];
+    // The list (slots 0..KM-1, descending); with the network merge, slots
+    // KM..KM+15 receive the queued batch during a merge.
+    constexpr bool kNet = KM >= 16 && PB == 16;
+    constexpr int KR = kNet ? KM + 16 : KM;
+    uint64_t key[KR];
+    float al[KR];
 #pragma unroll
-    for (int s = 0; s < KM; ++s) {
+    for (int s = 0; s < KR; ++s) {
         key[s] = 0;
         al[s] = 0.f;
     }
@@ -420,11 +477,25 @@ __device__ __forceinline__ void search_tile(
         }
     };
     auto merge_queue = [&]() {
-        for (int b = 0; b < PB; ++b) {
-            if (!__any(b < nq)) break;
-            if (b < nq) {
+        if constexpr (kNet) {
+            // The lane's queue (entries past nq read as empty) into the batch
+            // slots, then one network merge.
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
                 const uint64_t nk = ((uint64_t)q_hi[b * 64 + lane] << 32) | q_lo[b * 64 + lane];
-                if (nk > key[KM - 1]) insert(nk, q_al[b * 64 + lane]);
+                const float na = q_al[b * 64 + lane];
+                key[KM + b] = b < nq ? nk : 0;
+                al[KM + b] = b < nq ? na : 0.f;
+            }
+            net_merge<KM>(key, al);
+        } else {
+            for (int b = 0; b < PB; ++b) {
+                if (!__any(b < nq)) break;
+                if (b < nq) {
+                    const uint64_t nk =
+                        ((uint64_t)q_hi[b * 64 + lane] << 32) | q_lo[b * 64 + lane];
+                    if (nk > key[KM - 1]) insert(nk, q_al[b * 64 + lane]);
+                }
             }
         }
         nq = 0;

@@ -52,7 +52,9 @@ template <int KM, int NB>
 kb_status launch_one(const StackView &v, hipStream_t s) {
     constexpr int PB = KBMI_QUEUE;
     static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
-    if (KBMI_PERSIST_BS > 0) {
+    // The persistent order pays where gathers dominate (float32 planes); the
+    // 16-bit search keeps the super-strip order, which measured faster.
+    if (KBMI_PERSIST_BS > 0 && KBMI_FMT == KB_F32) {
         auto kernel = search_persistent_kernel<KM, NB, PB, KBMI_FMT>;
         const int grid = resident_workgroups(kernel);
         const int nseg = (v.w + 63) / 64;
