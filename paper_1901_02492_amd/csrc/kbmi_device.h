@@ -22,6 +22,9 @@
 #ifndef KBMI_PREFETCH
 #define KBMI_PREFETCH 1         // single-stack search: fetch the next table row early
 #endif
+#ifndef KBMI_PIPELINE
+#define KBMI_PIPELINE 1         // single-stack search: keep two velocities' gathers in flight
+#endif
 #ifndef KBMI_SUPER_W
 #define KBMI_SUPER_W 2          // tiles per XCD strip in the super-strip order (0: off)
 #endif
@@ -527,7 +530,44 @@ __device__ __forceinline__ void search_tile(
             for (int q = 0; q < NB / 2; ++q) asm volatile("" : "+v"(ss0[q]));
         }
     }
-    if (n_img <= NB && PF) {
+    // Two velocities' gathers fit beside the list up to KM = 50 (measured:
+    // longer lists spill registers with the second load buffer).
+    constexpr bool kPipe = PF && KBMI_PIPELINE && KM <= 50;
+    if (n_img <= NB && kPipe) {
+        // Two velocities in flight: the gathers of visit jj+1 are issued
+        // before visit jj is summed and scored, and the table row of jj+2 is
+        // fetched behind them (into the registers the row of jj+1 just left).
+        // The load buffers alternate, so the loop runs in pairs of visits; a
+        // visit past the end repeats the last row and is never scored.
+        i32x4 e[NB];
+        LoadT va[NB], vb[NB];
+        fetch(0, 0, e);
+        issue(e, va);
+        const int last = n_vel - 1;
+        int j_cur = visit[0];
+        int nxt = last < 1 ? last : 1;
+        fetch(nxt, 0, e);
+        int j_nxt = visit[nxt];
+        auto step = [&](int jj, LoadT(&cur)[NB], LoadT(&ahead)[NB]) {
+            issue(e, ahead);                       // visit jj + 1
+            __builtin_amdgcn_sched_barrier(0);
+            const int n2 = jj + 2 < last ? jj + 2 : last;
+            fetch(n2, 0, e);
+            const int j2 = visit[n2];
+            __builtin_amdgcn_sched_barrier(0);
+            float P = 0.f, F = 0.f;
+            accumulate(ss0, cur, P, F);
+            finish(j_cur, P, F, count(cur));
+            j_cur = j_nxt;
+            j_nxt = j2;
+        };
+        int jj = 0;
+        for (; jj + 1 < n_vel; jj += 2) {
+            step(jj, va, vb);
+            step(jj + 1, vb, va);
+        }
+        if (jj < n_vel) step(jj, va, vb);
+    } else if (n_img <= NB && PF) {
         // The next velocity's table row is fetched while this velocity's
         // gathers are in flight.
         i32x4 e[NB];
