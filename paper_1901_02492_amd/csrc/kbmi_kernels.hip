@@ -44,30 +44,39 @@ struct PsfTaps {
     float t[KB_MAX_PSF * KB_MAX_PSF];
 };
 
-constexpr int PP_TW = 64;       // output tile width (one wave's lanes)
+constexpr int PP_TW = 64;       // output tile width
 constexpr int PP_TH = 16;       // output tile height
-constexpr int PP_THREADS = 256; // 4 waves; each thread produces 4 rows of one column
-constexpr int PP_LW = PP_TW + KB_MAX_PSF - 1;
+constexpr int PP_THREADS = 256; // 4 waves; each thread produces 4 columns of one row
 constexpr int PP_LH = PP_TH + KB_MAX_PSF - 1;
 
+// psi = a (x) T and phi = w (x) T^2 (cross-correlations with zero padding) for
+// one 64 x 16 output tile of one image, with a = valid * img / var and
+// w = valid / var staged in LDS for the tile plus its halo as interleaved
+// pairs.  The PSF width PW is a compile-time constant: each thread computes 4
+// adjacent columns of one output row and, per PSF row, reads the
+// (4 + PW - 1)-pixel segment it needs once (16-byte LDS reads), so one LDS
+// read serves about three FMAs.  Per output the taps are summed row by row,
+// left to right.
+template <int PW>
 __global__ __launch_bounds__(PP_THREADS) void psi_phi_kernel(
     const float *__restrict__ img, const float *__restrict__ var,
-    const uint8_t *__restrict__ mask, int h, int w, int ph, int pw, PsfTaps psf,
+    const uint8_t *__restrict__ mask, int h, int w, int ph, PsfTaps psf,
     float2 *__restrict__ out, uint32_t *__restrict__ maxabs) {
-    __shared__ float s_a[PP_LH * PP_LW];
-    __shared__ float s_w[PP_LH * PP_LW];
-    __shared__ uint8_t s_ok[PP_LH * PP_LW];
+    constexpr int LW = PP_TW + PW - 1;        // staged columns (even: PW is odd)
+    constexpr int SEG = 4 + PW - 1;           // pixels one thread reads per PSF row
+    static_assert(PW % 2 == 1 && LW % 2 == 0 && SEG % 2 == 0, "odd PSF widths only");
+    __shared__ float2 s_aw[PP_LH * LW];
+    __shared__ uint8_t s_ok[PP_LH * LW];
 
     const int i = blockIdx.z;
     const int tx0 = blockIdx.x * PP_TW;
     const int ty0 = blockIdx.y * PP_TH;
-    const int cy = ph / 2, cx = pw / 2;
-    const int lh = PP_TH + ph - 1, lw = PP_TW + pw - 1;
+    const int cy = ph / 2, cx = PW / 2;
+    const int lh = PP_TH + ph - 1;
     const size_t plane = (size_t)i * (size_t)h * (size_t)w;
 
-    // Stage a = valid * img / var and w = valid / var for the tile plus halo.
-    for (int idx = threadIdx.x; idx < lh * lw; idx += PP_THREADS) {
-        const int ly = idx / lw, lx = idx - ly * lw;
+    for (int idx = threadIdx.x; idx < lh * LW; idx += PP_THREADS) {
+        const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = ty0 + ly - cy, gx = tx0 + lx - cx;
         float a = 0.f, wt = 0.f;
         uint8_t ok = 0;
@@ -82,53 +91,51 @@ __global__ __launch_bounds__(PP_THREADS) void psi_phi_kernel(
                 ok = 1;
             }
         }
-        s_a[ly * PP_LW + lx] = a;
-        s_w[ly * PP_LW + lx] = wt;
-        s_ok[ly * PP_LW + lx] = ok;
+        s_aw[idx] = make_float2(a, wt);
+        s_ok[idx] = ok;
     }
     __syncthreads();
 
-    const int lx = threadIdx.x & (PP_TW - 1);
-    const int ly0 = threadIdx.x / PP_TW;   // rows ly0, ly0 + 4, ly0 + 8, ly0 + 12
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     float ps[4] = {0.f, 0.f, 0.f, 0.f}, pf[4] = {0.f, 0.f, 0.f, 0.f};
     for (int u = 0; u < ph; ++u) {
-        for (int v = 0; v < pw; ++v) {
-            const float tv = psf.t[u * pw + v];
+        const float4 *row = reinterpret_cast<const float4 *>(s_aw + (ty + u) * LW + 4 * tx);
+        float2 seg[SEG];
+#pragma unroll
+        for (int q = 0; q < SEG / 2; ++q) {
+            const float4 x = row[q];
+            seg[2 * q] = make_float2(x.x, x.y);
+            seg[2 * q + 1] = make_float2(x.z, x.w);
+        }
+#pragma unroll
+        for (int v = 0; v < PW; ++v) {
+            const float tv = psf.t[u * PW + v];
             const float t2 = tv * tv;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int o = (ly0 + 4 * r + u) * PP_LW + lx + v;
-                ps[r] = fmaf(s_a[o], tv, ps[r]);
-                pf[r] = fmaf(s_w[o], t2, pf[r]);
+            for (int c = 0; c < 4; ++c) {
+                ps[c] = fmaf(seg[c + v].x, tv, ps[c]);
+                pf[c] = fmaf(seg[c + v].y, t2, pf[c]);
             }
         }
     }
+    const int gy = ty0 + ty;
+    float mp = 0.f, mf = 0.f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int gy = ty0 + ly0 + 4 * r, gx = tx0 + lx;
+    for (int c = 0; c < 4; ++c) {
+        const int gx = tx0 + 4 * tx + c;
         if (gy < h && gx < w) {
             float2 res = make_float2(0.f, 0.f);
-            if (s_ok[(ly0 + 4 * r + cy) * PP_LW + lx + cx]) {
+            if (s_ok[(ty + cy) * LW + 4 * tx + c + cx]) {
                 // phi >= 0 always; a valid pixel keeps a nonzero bit pattern.
-                res = make_float2(ps[r], pf[r] > 0.f ? pf[r] : -0.0f);
+                res = make_float2(ps[c], pf[c] > 0.f ? pf[c] : -0.0f);
+                mp = fmaxf(mp, fabsf(ps[c]));
+                mf = fmaxf(mf, pf[c]);
             }
             out[plane + (size_t)gy * w + gx] = res;
         }
     }
     if (maxabs != nullptr) {
-        // Per-image max |psi| and max phi for the 16-bit copy's scale: a block
-        // reduction, then one atomic max per block and plane (non-negative
-        // floats order like their bit patterns).
         __shared__ float s_red[2][PP_THREADS / 64];
-        float mp = 0.f, mf = 0.f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int gy = ty0 + ly0 + 4 * r, gx = tx0 + lx;
-            if (gy < h && gx < w && s_ok[(ly0 + 4 * r + cy) * PP_LW + lx + cx]) {
-                mp = fmaxf(mp, fabsf(ps[r]));
-                mf = fmaxf(mf, pf[r]);
-            }
-        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             mp = fmaxf(mp, __shfl_xor(mp, off));
@@ -496,9 +503,20 @@ kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mas
         kb_status ls = launch_status("lp_zero_kernel");
         if (ls != KB_OK) return ls;
     }
-    hipLaunchKernelGGL(psi_phi_kernel, grid, dim3(PP_THREADS), 0, s, img, var, mask, (int)h,
-                       (int)w, (int)psf_h, (int)psf_w, taps, reinterpret_cast<float2 *>(psi_phi),
-                       maxabs);
+    float2 *pp = reinterpret_cast<float2 *>(psi_phi);
+    switch (psf_w) {
+#define KB_PSF_W(PW)                                                                         \
+    case PW:                                                                                 \
+        hipLaunchKernelGGL(psi_phi_kernel<PW>, grid, dim3(PP_THREADS), 0, s, img, var, mask, \
+                           (int)h, (int)w, (int)psf_h, taps, pp, maxabs);                   \
+        break;
+        KB_PSF_W(1) KB_PSF_W(3) KB_PSF_W(5) KB_PSF_W(7) KB_PSF_W(9) KB_PSF_W(11) KB_PSF_W(13)
+        KB_PSF_W(15) KB_PSF_W(17) KB_PSF_W(19) KB_PSF_W(21) KB_PSF_W(23) KB_PSF_W(25)
+#undef KB_PSF_W
+    default:
+        return fail(KB_EUNSUPPORTED, "PSF width %lld is not an odd size <= %d", (long long)psf_w,
+                    KB_MAX_PSF);
+    }
     kb_status ls = launch_status("psi_phi_kernel");
     if (ls != KB_OK || !lp) return ls;
     hipLaunchKernelGGL(lp_scale_kernel, dim3((nsc + 255) / 256), dim3(256), 0, s, lp_scale, nsc);
