@@ -272,11 +272,20 @@ __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
 // for that trajectory.  Then every pixel's candidates are ranked by counting.
 // table: displacements in the original velocity order, rows of `stride`.
 // ---------------------------------------------------------------------------
+// One displacement of the table on the device: floor(v * tau + 0.5) as a
+// separate IEEE double multiply, add and floor (no contraction), clamped to
+// [-lim, lim], which rounds exactly as the host table does.
+__device__ inline int displacement(double v, double tau, int lim) {
+#pragma clang fp contract(off)
+    const double f = floor(v * tau + 0.5);
+    return (int)fmin(fmax(f, -(double)lim), (double)lim);
+}
+
 __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
     int64_t npix, int h, int w, int n_img, const float2 *__restrict__ planes,
-    const GatherEntry *__restrict__ table, int stride, int n_vel, int k_cand, int k,
-    const int32_t *__restrict__ cand_vel, float *__restrict__ nu, float *__restrict__ alpha,
-    int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
+    const double *__restrict__ tau, const double2 *__restrict__ vels, int n_vel, int k_cand,
+    int k, const int32_t *__restrict__ cand_vel, float *__restrict__ nu,
+    float *__restrict__ alpha, int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
     __shared__ uint64_t s_key[TK_THREADS];
     const int ppb = TK_THREADS / k_cand;
     const int t = (int)threadIdx.x;
@@ -292,15 +301,15 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
     const bool scored = active && j >= 0 && j < n_vel;
     if (scored) {
         const int y0 = (int)(p / w), x0 = (int)(p - (int64_t)y0 * w);
-        const GatherEntry *tj = table + (size_t)j * (size_t)stride;
+        const double2 vj = vels[j];
         float P = 0.f, F = 0.f;
         for (int i0 = 0; i0 < n_img; i0 += 8) {
             float2 v[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int i = i0 + b;
-                const GatherEntry &d = tj[i < n_img ? i : 0];
-                const int y = y0 + d.dy, x = x0 + d.dx;
+                const double ti = tau[i < n_img ? i : 0];
+                const int y = y0 + displacement(vj.y, ti, h), x = x0 + displacement(vj.x, ti, w);
                 const bool ok = i < n_img && (unsigned)y < (unsigned)h && (unsigned)x < (unsigned)w;
                 const size_t idx = ok ? ((size_t)i * h + y) * (size_t)w + x : 0;
                 const float2 raw = planes[idx];
@@ -346,13 +355,13 @@ __global__ void inv_scale_kernel(const float *__restrict__ scale, int n_img, int
 }
 
 kb_status launch_topk_rescore(int64_t npix, int h, int w, int n_img, const float2 *planes,
-                              const GatherEntry *table, int stride, int n_vel, int k_cand, int k,
-                              const int32_t *cv,
-                              float *nu, float *al, int32_t *vi, int16_t *no, hipStream_t stream) {
+                              const double *tau, const double2 *vels, int n_vel, int k_cand,
+                              int k, const int32_t *cv, float *nu, float *al, int32_t *vi,
+                              int16_t *no, hipStream_t stream) {
     const int64_t ppb = TK_THREADS / k_cand;
     const int64_t blocks = (npix + ppb - 1) / ppb;
     hipLaunchKernelGGL(topk_rescore_kernel, dim3((unsigned)blocks), dim3(TK_THREADS), 0, stream,
-                       npix, h, w, n_img, planes, table, stride, n_vel, k_cand, k, cv, nu, al, vi,
+                       npix, h, w, n_img, planes, tau, vels, n_vel, k_cand, k, cv, nu, al, vi,
                        no);
     return launch_status("topk_rescore_kernel");
 }
@@ -623,13 +632,22 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
             return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need,
                         workspace_bytes);
         hipStream_t s = (hipStream_t)stream;
-        st = upload_table(t, n_img, vel, n_vel, h, w, 8, workspace, s, false);
+        // tau_i = t_i - t_0 (as the host table computes it), then the velocities.
+        std::vector<double> host(static_cast<size_t>(n_img + 2 * n_vel));
+        for (int64_t i = 0; i < n_img; ++i) host[i] = t[i] - t[0];
+        std::memcpy(host.data() + n_img, vel, static_cast<size_t>(2 * n_vel) * sizeof(double));
+        const size_t vel_off = (static_cast<size_t>(n_img) * sizeof(double) + 15) / 16 * 16;
+        std::vector<char> staged(vel_off + static_cast<size_t>(2 * n_vel) * sizeof(double));
+        std::memcpy(staged.data(), host.data(), static_cast<size_t>(n_img) * sizeof(double));
+        std::memcpy(staged.data() + vel_off, vel, static_cast<size_t>(2 * n_vel) * sizeof(double));
+        st = staged_copy(workspace, staged.data(), staged.size(), s);
         if (st != KB_OK) return st;
+        char *ws = static_cast<char *>(workspace);
         return launch_topk_rescore(npix, (int)h, (int)w, (int)n_img,
                                    reinterpret_cast<const float2 *>(psi_phi_f32),
-                                   reinterpret_cast<const GatherEntry *>(workspace),
-                                   (int)table_stride(n_img), (int)n_vel, (int)k_cand, (int)k,
-                                   cand_vel, nu, alpha, vel_idx, nobs, s);
+                                   reinterpret_cast<const double *>(ws),
+                                   reinterpret_cast<const double2 *>(ws + vel_off), (int)n_vel,
+                                   (int)k_cand, (int)k, cand_vel, nu, alpha, vel_idx, nobs, s);
     }
     (void)workspace_bytes;
     return launch_topk(npix, (int)k_cand, (int)k, cand_nu, cand_alpha, cand_vel, cand_nobs, nu,
