@@ -90,9 +90,12 @@ kb_status launch_search_batch_bf16(int km, const BatchJob *jobs, int n_jobs, int
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) i32x4 global_i32x4;
-typedef __attribute__((address_space(1))) f32x4 global_f32x4;
-typedef __attribute__((address_space(1))) const int32_t global_i32;
+// The gather table, the visiting order and the inverse scales do not change
+// during a launch: they are read through the constant address space, so
+// their wave-uniform loads stay scalar whatever else the kernel writes.
+typedef __attribute__((address_space(4))) const i32x4 const_i32x4;
+typedef __attribute__((address_space(4))) const f32x4 const_f32x4;
+typedef __attribute__((address_space(4))) const int32_t const_i32;
 
 // Raw buffer loads with the descriptor as four plain words.
 __device__ u32x2 raw_load_b64(i32x4 rsrc, int voffset, int soffset, int aux)
@@ -395,17 +398,15 @@ __device__ __forceinline__ void search_tile(
     uint64_t thr = 0;   // admission threshold (list tail at the last merge)
     int nq = 0;         // queued candidates of this lane
 
-    const global_i32 *visit = (const global_i32 *)(const void *)vel_index;
+    const const_i32 *visit = (const const_i32 *)(const void *)vel_index;
     // Byte address of the start row in image 0; a table entry's offset moves
     // it to the displaced row of its image.
     const uint64_t row0 = reinterpret_cast<uint64_t>(planes) + (uint64_t)row * row_bytes;
     (void)img_bytes;
     // Fetch entries [i0, i0 + NB) of table row jj (wide scalar loads).
-    // The table is global memory (spelled out: in the batched search its
-    // address comes from a descriptor, and only global loads become scalar).
     auto fetch = [&](int jj, int i0, i32x4(&e)[NB]) {
-        const global_i32x4 *t4 =
-            (const global_i32x4 *)(const void *)(disp + (size_t)jj * disp_stride + i0);
+        const const_i32x4 *t4 =
+            (const const_i32x4 *)(const void *)(disp + (size_t)jj * disp_stride + i0);
 #pragma unroll
         for (int b = 0; b < NB; ++b) e[b] = t4[b];
     };
@@ -434,7 +435,7 @@ __device__ __forceinline__ void search_tile(
     // [i0, i0 + NB), uniform values.
     typedef f32x4 Scales[NB / 2];
     auto load_scales = [&](int i0, Scales &ss) {
-        const global_f32x4 *sc4 = (const global_f32x4 *)(const void *)(inv_scale + i0);
+        const const_f32x4 *sc4 = (const const_f32x4 *)(const void *)(inv_scale + i0);
 #pragma unroll
         for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
     };
@@ -678,6 +679,8 @@ __global__ __launch_bounds__(64, 2) void search_persistent_kernel(
     __shared__ uint32_t lds[search_lds_words<KM, PB>()];
     uint32_t *xcd_count = sync + (blockIdx.x & 7);
     const uint32_t per_xcd = gridDim.x >> 3;
+    int spin = pm.spin;   // 0 once a wait has timed out (the XCD's workgroups are
+                          // not all resident, e.g. beside another launch)
     for (int gen = 0; gen < pm.generations; ++gen) {
         int row, seg;
         if (pm.map(gen, (int)blockIdx.x, row, seg))
@@ -690,12 +693,14 @@ __global__ __launch_bounds__(64, 2) void search_persistent_kernel(
         if (threadIdx.x == 0)
             __hip_atomic_fetch_add(xcd_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t target = (uint32_t)(gen + 1) * per_xcd;
-        for (int i = 0; i < pm.spin; ++i) {
+        int i = 0;
+        for (; i < spin; ++i) {
             if (__hip_atomic_load(xcd_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
                 target)
                 break;
             __builtin_amdgcn_s_sleep(8);
         }
+        if (i == spin) spin = 0;
     }
 }
 
@@ -721,13 +726,24 @@ __global__ __launch_bounds__(64, 2) void search_batch_kernel(const BatchJob *__r
         if (jobs[mid].block_begin <= t) lo = mid;
         else hi = mid - 1;
     }
-    const BatchJob &jb = jobs[lo];
+    // The descriptor is the same for the whole wave; reading its fields
+    // through readfirstlane keeps them (and the table and buffer descriptors
+    // derived from them) in scalar registers.
+    const BatchJob &jb = jobs[__builtin_amdgcn_readfirstlane(lo)];
+    auto u32 = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+    auto uptr = [](auto *p) {
+        const uint64_t v = reinterpret_cast<uint64_t>(p);
+        const uint64_t lo32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+        const uint64_t hi32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+        return reinterpret_cast<decltype(p)>(lo32 | (hi32 << 32));
+    };
     int row, seg;
-    const int h = jb.h;
-    strip_tile(t - jb.block_begin, jb.nseg, h, jb.strip, row, seg);
-    search_tile<KM, 16, PB, FMT, false>(lds, jb.planes, jb.inv_scale, jb.n_img, h, jb.w, jb.disp,
-                                 jb.disp_stride, jb.vel_index, jb.n_vel, k_cand, row, seg,
-                                 jb.cand_nu, jb.cand_alpha, jb.cand_vel, jb.cand_nobs);
+    const int h = u32(jb.h);
+    strip_tile(t - u32(jb.block_begin), u32(jb.nseg), h, u32(jb.strip), row, seg);
+    search_tile<KM, 16, PB, FMT, false>(
+        lds, uptr(jb.planes), uptr(jb.inv_scale), u32(jb.n_img), h, u32(jb.w), uptr(jb.disp),
+        u32(jb.disp_stride), uptr(jb.vel_index), u32(jb.n_vel), k_cand, row, seg,
+        uptr(jb.cand_nu), uptr(jb.cand_alpha), uptr(jb.cand_vel), uptr(jb.cand_nobs));
 }
 
 }  // namespace

@@ -278,9 +278,16 @@ class GpuExecutor:
             for hd in handles:
                 s.wait_event(hd["prepared"])
             for kc, hs in groups.items():
-                jobs = [dict(planes=hd["src"], t=hd["req"].t, vel=hd["req"].vel,
-                             out=hd["cand"], lp_scale=hd["scale"]) for hd in hs]
-                lib.search_batch(jobs, kc, stream=s)
+                if len(hs) == 1:
+                    # A stack alone: the single-stack search (same per-tile
+                    # arithmetic, so the same results) in its fastest order.
+                    hd = hs[0]
+                    lib.search(hd["src"], hd["req"].t, hd["req"].vel, kc, out=hd["cand"],
+                               workspace=hd["ws"], stream=s, lp_scale=hd["scale"])
+                else:
+                    jobs = [dict(planes=hd["src"], t=hd["req"].t, vel=hd["req"].vel,
+                                 out=hd["cand"], lp_scale=hd["scale"]) for hd in hs]
+                    lib.search_batch(jobs, kc, stream=s)
                 for hd in hs:
                     n = hd["img"].shape[0]
                     rescore = None if self.lp is None else (hd["planes"], hd["req"].t,
