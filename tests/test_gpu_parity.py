@@ -89,6 +89,33 @@ def test_persistent_order_ragged_frame(torch_dev):
     _full_check(torch_dev, s)
 
 
+def test_concurrent_persistent_searches(torch_dev):
+    """Two searches large enough for the persistent order, launched on two
+    streams at once, compete for wave slots (so their per-XCD pacing waits can
+    time out); each must still return exactly what it returns alone."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    dev = torch.device("cuda:0")
+    s = synth.random_stack(21, n=8, h=520, w=1000, n_vel=60, k=50, psf_size=5, vmax=60.0)
+    img = torch.from_numpy(s.img).to(dev)
+    var = torch.from_numpy(s.var).to(dev)
+    mask = torch.from_numpy(s.mask).to(dev)
+    planes = lib.make_psi_phi(img, var, mask, s.psf)
+    n, h, w = s.img.shape
+    alone = parity.to_numpy(lib.search(planes, s.t, s.vel, 50))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(device=dev) for _ in range(2)]
+    outs = []
+    for st in streams:
+        with torch.cuda.stream(st):
+            ws = lib.alloc_workspace(n, h, w, s.vel.shape[0], dev)
+            outs.append((lib.search(planes, s.t, s.vel, 50, workspace=ws), ws))
+    torch.cuda.synchronize()
+    for res, _ in outs:
+        for a, b in zip(parity.to_numpy(res), alone):
+            assert np.array_equal(a, b)
+
+
 def test_fully_masked_image_and_bad_pixels(torch_dev):
     s = synth.random_stack(11, n=4, h=30, w=70, n_vel=10, k=4, psf_size=3)
     s.mask[2] = 1
