@@ -82,3 +82,56 @@ def test_unweighted_phi_is_caught(monkeypatch):
 def test_tie_break_by_descending_index_is_caught(monkeypatch):
     _patch(monkeypatch, "rank_topk", lambda nu, k: (nu.shape[0] - 1 - np.argsort(-nu[::-1], axis=0, kind="stable"))[:k])
     assert _fails(pins.test_rank_topk_equals_sorted_with_ties)
+
+
+# Light-curve filter: each planted mistake must fail a pin of
+# test_oracle_lightcurve.py.
+
+from oracle import lightcurve as lcf  # noqa: E402
+from tests import test_oracle_lightcurve as lcpins  # noqa: E402
+
+
+def test_estimate_that_uses_the_observation_itself_is_caught(monkeypatch):
+    orig = lcf.kalman_loo
+
+    def with_self(lc_psi, lc_phi, obs, tau, q):
+        J, H = orig(lc_psi, lc_phi, obs, tau, q)
+        return J + lc_phi * obs, H + lc_psi * obs
+    monkeypatch.setattr(lcf, "kalman_loo", with_self)
+    assert _fails(lcpins.test_loo_estimate_is_the_random_walk_posterior, 0.5)
+    assert _fails(lcpins.test_null_residuals_are_standard_normal, 0.0)
+
+
+def test_ignored_process_noise_is_caught(monkeypatch):
+    orig = lcf._one_direction
+    monkeypatch.setattr(lcf, "_one_direction",
+                        lambda lp, lf, o, tau, q, order: orig(lp, lf, o, tau, 0.0, order))
+    assert _fails(lcpins.test_loo_estimate_is_the_random_walk_posterior, 20.0)
+    assert _fails(lcpins.test_null_residuals_are_standard_normal, 1.0)
+
+
+def test_forward_only_filter_is_caught(monkeypatch):
+    def forward(lc_psi, lc_phi, obs, tau, q):
+        return lcf._one_direction(lc_psi, lc_phi, obs, np.asarray(tau, np.float64), q,
+                                  range(lc_psi.shape[1]))
+    monkeypatch.setattr(lcf, "kalman_loo", forward)
+    assert _fails(lcpins.test_loo_estimate_is_the_random_walk_posterior, 0.5)
+
+
+def test_residual_variance_without_the_estimate_term_is_caught(monkeypatch):
+    def narrow(lc_psi, lc_phi, obs, J, H):
+        a = lc_psi * J - lc_phi * H
+        d = (lc_phi * J) * J
+        pos = obs & (d > 0)
+        return np.where(pos, (a * a) / np.where(pos, d, 1.0), 0.0)
+    monkeypatch.setattr(lcf, "residual_ratio", narrow)
+    assert _fails(lcpins.test_null_exceedance_rate_is_the_normal_tail, 2.0, 0.0)
+    assert _fails(lcpins.test_null_residuals_are_standard_normal, 0.0)
+
+
+def test_single_pass_clip_is_caught(monkeypatch):
+    def one_pass(lc_psi, lc_phi, obs, tau, q, sigma_cut):
+        J, H = lcf.kalman_loo(lc_psi, lc_phi, obs, tau, q)
+        return obs & (lcf.residual_ratio(lc_psi, lc_phi, obs, J, H) > sigma_cut ** 2)
+    monkeypatch.setattr(lcf, "clip", one_pass)
+    assert _fails(lcpins.test_planted_outlier_is_the_only_rejection)
