@@ -9,6 +9,9 @@
  *                     coadd, Sec. 2.2) and keep the k_cand best per start pixel
  *   kb_topk           order each start pixel's candidates and keep k
  *   kb_displacements  the integer pixel offsets every kernel uses   (Sec. 2.2)
+ * and one stage after it:
+ *   kb_lightcurve_filter  drop outlying observations from each candidate's
+ *                     light curve and refit nu, alpha           (Sec. 3.3)
  *
  * Conventions shared by every call
  *   - Pixel (x, y) is column x, row y of a row-major [h][w] frame; integer
@@ -52,6 +55,9 @@ extern "C" {
 #define KB_MAX_KCAND 64
 /* Largest PSF side length kb_make_psi_phi accepts (odd sizes only). */
 #define KB_MAX_PSF 25
+/* Largest image count kb_lightcurve_filter accepts (one bit per image in its
+ * rejection mask). */
+#define KB_MAX_LC_IMAGES 64
 
 typedef enum kb_status {
     KB_OK = 0,
@@ -192,6 +198,54 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
                   int64_t k_cand, int64_t k,
                   float *nu, float *alpha, int32_t *vel_idx, int16_t *nobs,
                   void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * kb_lightcurve_filter - outlier filter on each candidate's light curve and
+ * refit of its likelihood (Sec. 3.3, filtering of candidate trajectories; the
+ * paper names the filter only as a Kalman-filter variant, this is the variant
+ * implemented).
+ * Candidate (x0, y0, j) observes image i when its trajectory pixel (the
+ * displacements of kb_displacements) is inside the frame and valid; the
+ * observation's flux estimate is psi_i/phi_i with variance 1/phi_i.  The flux
+ * is modelled as a random walk with variance q per day (q = 0: constant).  An
+ * information-form Kalman filter runs forward and backward over the
+ * observations; the estimate at observation k from all the others has
+ * information J_k = Jf_k + Jb_k and H_k = Hf_k + Hb_k (estimate H_k/J_k), and
+ *     r_k = (psi_k J_k - phi_k H_k)^2 / ((phi_k J_k)(J_k + phi_k))
+ * is its squared standardised residual (0 if the divisor is not positive).
+ * While the largest r_k (lowest image index among equal values) exceeds
+ * sigma_cut^2, that observation is dropped and the filter is rerun on the
+ * rest.  Then Psi', Phi' are summed over the kept observations in image order,
+ * nu' = Psi'/sqrt(Phi'), alpha' = Psi'/Phi' (nu' = -inf, alpha' = 0 if
+ * Phi' <= 0), n_obs' = number kept.  All filter arithmetic is IEEE double with
+ * every operation separately rounded (prediction: d = 1 + (q dtau) J,
+ * J <- J/d, H <- H/d, dtau from tau_i = t_i - t_0; update: J += phi_i,
+ * H += psi_i), so each decision is reproducible from the float32 planes.
+ *   psi_phi    device, float32 [n_img][h][w][2] planes from kb_make_psi_phi
+ *              (invalid pixels hold (+0, +0)).
+ *   t, vel     host, as for kb_displacements; n_img <= KB_MAX_LC_IMAGES.
+ *   cand_vel   device, int32 [h][w][k] velocity indices, e.g. kb_topk's output;
+ *              an index outside [0, n_vel) yields nu' = -inf, alpha' = 0,
+ *              n_obs' = 0.
+ *   sigma_cut  the cut in standard deviations (5 in the paper), > 0.
+ *   q          process-noise variance of the flux per day, >= 0.
+ *   nu, alpha  device out, float32 [h][w][k], same order as cand_vel (not
+ *              re-ranked); they may alias kb_topk's nu and alpha outputs.
+ *   nobs       device out, int16 [h][w][k].
+ *   rejected   device out or NULL, uint64 [h][w][k]: bit i set when image i
+ *              was an observation and was dropped.
+ *   workspace  device, 256-byte aligned, >= kb_search_workspace_bytes(n_img,
+ *              h, w, n_vel) bytes; tau and the velocities are copied into it
+ *              asynchronously on `stream`.
+ * Errors: KB_EINVAL for null pointers, bad sizes, times or velocities,
+ * sigma_cut not finite and positive, q not finite and >= 0; KB_ENOMEM for a
+ * short workspace; KB_EUNSUPPORTED for n_img > KB_MAX_LC_IMAGES.
+ */
+kb_status kb_lightcurve_filter(const float *psi_phi, int64_t n_img, int64_t h, int64_t w,
+                               const double *t, const double *vel, int64_t n_vel,
+                               const int32_t *cand_vel, int64_t k, double sigma_cut, double q,
+                               float *nu, float *alpha, int16_t *nobs, uint64_t *rejected,
+                               void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Batched search (serving).  One stack of a batch: the kb_search arguments of

@@ -9,7 +9,7 @@ search, each candidate's light curve (its per-image likelihood values along
 the trajectory) is run through a Kalman-type filter; observations more than
 five standard deviations from the filter's flux estimate at that observation
 are dropped, and the likelihood is recomputed from the remaining ones.  The
-paper names the filter only as a variation on the Kalman filter, so the
+paper names the filter only as a Kalman-filter variant, so the
 variant below is a reading of that passage:
 
   1. Observations.  Image i observes candidate (x0, y0, j) when the trajectory
@@ -51,7 +51,8 @@ import numpy as np
 
 from .core import displacements, scores
 
-__all__ = ["light_curves", "kalman_loo", "residual_ratio", "clip", "refit", "lightcurve_filter"]
+__all__ = ["light_curves", "light_curves_at", "kalman_loo", "residual_ratio", "clip", "refit",
+           "filter_curves", "lightcurve_filter"]
 
 
 def light_curves(psi, phi, ok, t, vel, ys, xs, js):
@@ -85,6 +86,34 @@ def light_curves(psi, phi, ok, t, vel, ys, xs, js):
     obs[inb] = ok[img[inb], yy[inb], xx[inb]]
     lc_psi[~obs] = 0.0
     lc_phi[~obs] = 0.0
+    return lc_psi, lc_phi, obs
+
+
+def light_curves_at(plane_fn, n, h, w, t, vel, ys, xs, js):
+    """As light_curves, evaluating the planes only at the visited pixels:
+    plane_fn(i, yy, xx) -> (psi, phi, valid) for in-frame pixels of image i."""
+    ys = np.asarray(ys, dtype=np.int64)
+    xs = np.asarray(xs, dtype=np.int64)
+    js = np.asarray(js, dtype=np.int64)
+    vel = np.asarray(vel, dtype=np.float64).reshape(-1, 2)
+    disp = displacements(t, vel)
+    good = (js >= 0) & (js < vel.shape[0])
+    d = disp[np.where(good, js, 0)]
+    lc_psi = np.zeros((js.size, n))
+    lc_phi = np.zeros((js.size, n))
+    obs = np.zeros((js.size, n), dtype=bool)
+    for i in range(n):
+        yy = ys + d[:, i, 1]
+        xx = xs + d[:, i, 0]
+        inb = good & (yy >= 0) & (yy < h) & (xx >= 0) & (xx < w)
+        if not inb.any():
+            continue
+        ps, ph, ok = plane_fn(i, yy[inb], xx[inb])
+        sel = np.nonzero(inb)[0]
+        ok = np.asarray(ok, dtype=bool)
+        obs[sel, i] = ok
+        lc_psi[sel[ok], i] = np.asarray(ps, dtype=np.float64)[ok]
+        lc_phi[sel[ok], i] = np.asarray(ph, dtype=np.float64)[ok]
     return lc_psi, lc_phi, obs
 
 
@@ -164,6 +193,14 @@ def refit(lc_psi, lc_phi, keep):
     return nu, alpha, keep.sum(axis=1)
 
 
+def filter_curves(lc_psi, lc_phi, obs, t, sigma_cut=5.0, q=0.0):
+    """Steps 3 to 5 on given light curves: dict(nu, alpha, nobs, rejected)."""
+    t = np.asarray(t, dtype=np.float64)
+    rej = clip(lc_psi, lc_phi, obs, t - t[0], q, sigma_cut)
+    nu, alpha, nobs = refit(lc_psi, lc_phi, obs & ~rej)
+    return dict(nu=nu, alpha=alpha, nobs=nobs, rejected=rej)
+
+
 def lightcurve_filter(psi, phi, ok, t, vel, ys, xs, js, sigma_cut=5.0, q=0.0):
     """The whole filter for candidates (ys, xs, js).
 
@@ -171,10 +208,7 @@ def lightcurve_filter(psi, phi, ok, t, vel, ys, xs, js, sigma_cut=5.0, q=0.0):
     of the dropped observations, plus the light curves (lc_psi, lc_phi, obs)
     for the tests.
     """
-    t = np.asarray(t, dtype=np.float64)
-    tau = t - t[0]
     lc_psi, lc_phi, obs = light_curves(psi, phi, ok, t, vel, ys, xs, js)
-    rej = clip(lc_psi, lc_phi, obs, tau, q, sigma_cut)
-    nu, alpha, nobs = refit(lc_psi, lc_phi, obs & ~rej)
-    return dict(nu=nu, alpha=alpha, nobs=nobs, rejected=rej,
-                lc_psi=lc_psi, lc_phi=lc_phi, obs=obs)
+    out = filter_curves(lc_psi, lc_phi, obs, t, sigma_cut, q)
+    out.update(lc_psi=lc_psi, lc_phi=lc_phi, obs=obs)
+    return out

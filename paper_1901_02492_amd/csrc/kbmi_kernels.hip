@@ -270,17 +270,6 @@ __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
 // the float32 search (image order, out-of-frame terms adding +0, the same
 // score expressions), so a re-scored entry is bitwise the plain path's value
 // for that trajectory.  Then every pixel's candidates are ranked by counting.
-// table: displacements in the original velocity order, rows of `stride`.
-// ---------------------------------------------------------------------------
-// One displacement of the table on the device: floor(v * tau + 0.5) as a
-// separate IEEE double multiply, add and floor (no contraction), clamped to
-// [-lim, lim], which rounds exactly as the host table does.
-__device__ inline int displacement(double v, double tau, int lim) {
-#pragma clang fp contract(off)
-    const double f = floor(v * tau + 0.5);
-    return (int)fmin(fmax(f, -(double)lim), (double)lim);
-}
-
 __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
     int64_t npix, int h, int w, int n_img, const float2 *__restrict__ planes,
     const double *__restrict__ tau, const double2 *__restrict__ vels, int n_vel, int k_cand,
@@ -376,6 +365,8 @@ kb_status launch_topk(int64_t npix, int k_cand, int k, const float *cn, const fl
     return launch_status("topk_kernel");
 }
 
+}  // namespace
+
 kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
     if (n_img < 1 || n_img > 32767)
         return fail(KB_EINVAL, "n_img must be in [1, 32767] (got %lld)", (long long)n_img);
@@ -395,6 +386,7 @@ kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
 // most kStagingPerDevice; beyond that a call waits for one of them) until the
 // process ends.
 // ---------------------------------------------------------------------------
+namespace {
 struct StagingBuffer {
     void *host;
     size_t cap;
@@ -404,6 +396,7 @@ struct StagingBuffer {
 constexpr int kStagingPerDevice = 32;
 std::mutex g_staging_mu;
 std::vector<StagingBuffer *> g_staging;
+}  // namespace
 
 kb_status staged_copy(void *dst, const void *src, size_t bytes, hipStream_t stream) {
     int dev = 0;
@@ -455,6 +448,20 @@ kb_status staged_copy(void *dst, const void *src, size_t bytes, hipStream_t stre
     if (e != hipSuccess) return fail(KB_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
     return KB_OK;
 }
+
+kb_status upload_tau_vel(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+                         void *workspace, hipStream_t stream, size_t *vel_off) {
+    // tau_i = t_i - t_0, as the host table computes it, then the velocities.
+    const size_t off = (static_cast<size_t>(n_img) * sizeof(double) + 15) / 16 * 16;
+    std::vector<char> staged(off + static_cast<size_t>(2 * n_vel) * sizeof(double));
+    double *tau = reinterpret_cast<double *>(staged.data());
+    for (int64_t i = 0; i < n_img; ++i) tau[i] = t[i] - t[0];
+    std::memcpy(staged.data() + off, vel, static_cast<size_t>(2 * n_vel) * sizeof(double));
+    *vel_off = off;
+    return staged_copy(workspace, staged.data(), staged.size(), stream);
+}
+
+namespace {
 
 // Copy the gather table (for planes of `pix_bytes` bytes per pair) and the
 // visiting order into the workspace, asynchronously on `stream`.
@@ -632,15 +639,8 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
             return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need,
                         workspace_bytes);
         hipStream_t s = (hipStream_t)stream;
-        // tau_i = t_i - t_0 (as the host table computes it), then the velocities.
-        std::vector<double> host(static_cast<size_t>(n_img + 2 * n_vel));
-        for (int64_t i = 0; i < n_img; ++i) host[i] = t[i] - t[0];
-        std::memcpy(host.data() + n_img, vel, static_cast<size_t>(2 * n_vel) * sizeof(double));
-        const size_t vel_off = (static_cast<size_t>(n_img) * sizeof(double) + 15) / 16 * 16;
-        std::vector<char> staged(vel_off + static_cast<size_t>(2 * n_vel) * sizeof(double));
-        std::memcpy(staged.data(), host.data(), static_cast<size_t>(n_img) * sizeof(double));
-        std::memcpy(staged.data() + vel_off, vel, static_cast<size_t>(2 * n_vel) * sizeof(double));
-        st = staged_copy(workspace, staged.data(), staged.size(), s);
+        size_t vel_off = 0;
+        st = upload_tau_vel(t, n_img, vel, n_vel, workspace, s, &vel_off);
         if (st != KB_OK) return st;
         char *ws = static_cast<char *>(workspace);
         return launch_topk_rescore(npix, (int)h, (int)w, (int)n_img,

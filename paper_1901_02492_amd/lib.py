@@ -34,6 +34,9 @@ _SIGNATURES = {
                                  _p, _p, _sz, _p]),
     "kb_topk": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64,
                                _p, _p, _p, _p, _p, _sz, _p]),
+    "kb_lightcurve_filter": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, _p, _i64,
+                                            ctypes.c_double, ctypes.c_double, _p, _p, _p, _p, _p,
+                                            _sz, _p]),
     "kb_search_batch_workspace_bytes": (_sz, [_p, _i64]),
     "kb_search_batch": (ctypes.c_int, [_p, _i64, _i32, _i64, _p, _sz, _p]),
 }
@@ -231,6 +234,34 @@ def topk(cand, k, n_img, out=None, stream=None, rescore=None):
                           _dev(vi, torch.int32, "vel"), _dev(no, torch.int16, "nobs"), wsp, wsb,
                           _stream(stream)))
     return out
+
+
+def lightcurve_filter(planes, t, vel, cand_vel, sigma_cut=5.0, q=0.0, out=None,
+                      workspace=None, stream=None, rejected=False):
+    """kb_lightcurve_filter: (nu, alpha, nobs) [H][W][k] refit after dropping
+    outlying observations from each candidate's light curve, plus the uint64
+    rejection masks (as int64) when rejected=True."""
+    torch = _torch()
+    n, h, w, _ = planes.shape
+    t = _host_f64(t)
+    vel = _host_f64(vel, 2)
+    k = cand_vel.shape[-1]
+    dev = planes.device
+    if out is None:
+        out = (torch.empty((h, w, k), dtype=torch.float32, device=dev),
+               torch.empty((h, w, k), dtype=torch.float32, device=dev),
+               torch.empty((h, w, k), dtype=torch.int16, device=dev))
+    nu, al, no = out
+    rej = torch.empty((h, w, k), dtype=torch.int64, device=dev) if rejected else None
+    if workspace is None:
+        workspace = alloc_workspace(n, h, w, vel.shape[0], dev)
+    _check(load().kb_lightcurve_filter(
+        _dev(planes, torch.float32, "psi_phi"), n, h, w, t.ctypes.data, vel.ctypes.data,
+        vel.shape[0], _dev(cand_vel, torch.int32, "cand_vel"), k, float(sigma_cut), float(q),
+        _dev(nu, torch.float32, "nu"), _dev(al, torch.float32, "alpha"),
+        _dev(no, torch.int16, "nobs"), None if rej is None else _dev(rej, torch.int64, "rejected"),
+        _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)))
+    return (nu, al, no, rej) if rejected else (nu, al, no)
 
 
 def _job_array(jobs):

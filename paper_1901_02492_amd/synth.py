@@ -170,16 +170,34 @@ def _smooth_sigma(rng, n, h, w, amp=0.2):
     return out
 
 
+def add_flashes(img: np.ndarray, var: np.ndarray, n_flash: int, rng, psf_sigma: float,
+                s2: float, snr=(10.0, 100.0)) -> np.ndarray:
+    """Point sources that appear in one image only (a fast or bright object
+    crossing a trajectory in a single exposure, Sec. 3.3), each at a random
+    image, position and single-image signal-to-noise in `snr`.  Returns
+    float64 [n_flash][4]: image, x, y, flux."""
+    n, h, w = img.shape
+    out = np.zeros((n_flash, 4))
+    for f in range(n_flash):
+        i = int(rng.integers(0, n))
+        x, y = rng.uniform(0, w), rng.uniform(0, h)
+        flux = rng.uniform(*snr) / math.sqrt(s2 / float(var[i, int(y), int(x)]))
+        render_point_source(img[i], x, y, flux, psf_sigma)
+        out[f] = (i, x, y, flux)
+    return out
+
+
 def survey_stack(cfg: int = 1, n_nights: int = 3, epochs: int = 5, h: int = 4096,
                  w: int = 4096, n_src: int = 100, snr=(5.0, 20.0), n_speeds: int = 25,
                  n_angles: int = 24, k: int = 50, mask_frac: float = 0.01,
-                 psf_sigma: float = 1.5, psf_size: int = 11) -> Stack:
+                 psf_sigma: float = 1.5, psf_size: int = 11, n_flash: int = 0) -> Stack:
     """Survey-shaped stack: nights x epochs images 0.06 d apart within a night
     (Sec. 3.1: ~5 visits per night over three nights), smoothly varying noise
     sigma in [0.8, 1.2] with var = sigma^2, random 1% masks per image, an
     11x11 Gaussian PSF (sigma 1.5 px), injected sources at speeds 80-400 px/d
     within +-0.5 rad of the x axis, and a speed x angle velocity grid over the
-    same ranges.  Defaults: 15 x 4096^2, 600 velocities, K = 50."""
+    same ranges.  Defaults: 15 x 4096^2, 600 velocities, K = 50.  n_flash > 0
+    adds that many single-image sources (add_flashes), drawn after the rest."""
     n = n_nights * epochs
     t = np.array([night + 0.06 * e for night in range(n_nights) for e in range(epochs)],
                  dtype=np.float64)
@@ -217,6 +235,8 @@ def survey_stack(cfg: int = 1, n_nights: int = 3, epochs: int = 5, h: int = 4096
             render_point_source(img[i], x0 + vx * (t[i] - t[0]), y0 + vy * (t[i] - t[0]),
                                 flux, psf_sigma)
         srcs.append((x0, y0, vx, vy, flux))
+    if n_flash:
+        add_flashes(img, var, n_flash, np.random.default_rng(seed_for(cfg, 3)), psf_sigma, s2)
     speeds = np.linspace(80.0, 400.0, n_speeds)
     angles = np.linspace(-0.5, 0.5, n_angles)
     return Stack(img, var, mask, t, psf, velocity_grid_polar(speeds, angles), k,
@@ -226,10 +246,10 @@ def survey_stack(cfg: int = 1, n_nights: int = 3, epochs: int = 5, h: int = 4096
 
 def random_stack(seed: int, n: int, h: int, w: int, n_vel: int, k: int,
                  psf_size: int = 5, psf_sigma: float = 1.0, mask_frac: float = 0.05,
-                 vmax: float = 40.0, tmax: float = 1.0) -> Stack:
+                 vmax: float = 40.0, tmax: float = 1.0, n_flash: int = 0) -> Stack:
     """Small randomized stack for parity sweeps: random times, noise, variance
     and masks; velocities drawn uniformly in [-vmax, vmax]^2 so tracks leave
-    the frame on every side."""
+    the frame on every side.  n_flash > 0 adds single-image sources."""
     rng = np.random.default_rng(SEED_BASE + 7919 * seed)
     t = np.sort(rng.uniform(0.0, tmax, size=n))
     t[0] = 0.0
@@ -244,7 +264,11 @@ def random_stack(seed: int, n: int, h: int, w: int, n_vel: int, k: int,
         for i in range(n):
             render_point_source(img[i], x0 + vx * t[i], y0 + vy * t[i], 20.0, psf_sigma)
         src.append((x0, y0, vx, vy, 20.0))
-    return Stack(img, var, mask, t, psf_gaussian(psf_sigma, psf_size), vel, k,
+    psf = psf_gaussian(psf_sigma, psf_size)
+    if n_flash:
+        add_flashes(img, var, n_flash, np.random.default_rng(SEED_BASE + 7919 * seed + 1),
+                    psf_sigma, float(np.sum(psf.astype(np.float64) ** 2)))
+    return Stack(img, var, mask, t, psf, vel, k,
                  np.array(src, dtype=np.float64).reshape(-1, 5), name=f"random{seed}")
 
 

@@ -175,3 +175,33 @@ def test_batch_rejects_bad_jobs_before_enqueue():
     assert L.kb_search_batch(ctypes.addressof(arr), 1, 1, 2, fake, 1 << 20, None) == lib.KB_EINVAL
     assert L.kb_search_batch(ctypes.addressof(arr), 1, 0, 2, fake, 16, None) == lib.KB_ENOMEM
     assert L.kb_search_batch_workspace_bytes(ctypes.addressof(arr), 1) > 0
+
+
+def _lc_call(n=3, h=8, w=8, t=None, nv=4, k=2, cut=5.0, q=0.0, ws_bytes=1 << 20, ws=1 << 20,
+             cand=1 << 20):
+    L = lib.load()
+    fake = 1 << 20
+    t = np.arange(n, dtype=np.float64) if t is None else t
+    v = np.zeros((nv, 2))
+    st = L.kb_lightcurve_filter(fake, n, h, w, t.ctypes.data, v.ctypes.data, nv, cand, k, cut, q,
+                                fake, fake, fake, None, ws, ws_bytes, None)
+    return st, L.kb_last_error().decode()
+
+
+def test_lightcurve_filter_argument_checks():
+    st, msg = _lc_call(n=65, t=np.arange(65, dtype=np.float64))
+    assert st == lib.KB_EUNSUPPORTED and "64" in msg
+    assert _lc_call(cut=0.0)[0] == lib.KB_EINVAL
+    assert _lc_call(cut=float("nan"))[0] == lib.KB_EINVAL
+    assert _lc_call(cut=1e200)[0] == lib.KB_EINVAL            # cut^2 overflows
+    assert _lc_call(q=-1.0)[0] == lib.KB_EINVAL
+    assert _lc_call(q=float("inf"))[0] == lib.KB_EINVAL
+    assert _lc_call(k=0)[0] == lib.KB_EINVAL
+    assert _lc_call(nv=0)[0] == lib.KB_EINVAL
+    assert _lc_call(cand=None)[0] == lib.KB_EINVAL
+    assert _lc_call(ws=None)[0] == lib.KB_EINVAL
+    assert _lc_call(ws=(1 << 20) + 8)[0] == lib.KB_EINVAL   # misaligned
+    st, msg = _lc_call(ws_bytes=16)
+    assert st == lib.KB_ENOMEM and "workspace" in msg
+    st, msg = _lc_call(t=np.array([0.0, 2.0, 1.0]))
+    assert st == lib.KB_EINVAL and "non-decreasing" in msg

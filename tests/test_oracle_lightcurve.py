@@ -197,3 +197,20 @@ def test_filter_on_a_stack_gathers_the_trajectory_pixels():
     F = (out["lc_phi"] * keep).sum(axis=1)
     nu, al = core.scores(P, F)
     np.testing.assert_allclose(out["nu"][:3], nu[:3], rtol=1e-12)
+
+
+def test_sampled_light_curves_equal_the_full_gather():
+    rng = np.random.default_rng(31)
+    n, h, w = 5, 16, 18
+    t = np.array([0.0, 0.1, 0.2, 1.0, 1.1])
+    psi = rng.normal(0.0, 1.0, (n, h, w))
+    phi = rng.uniform(0.5, 1.5, (n, h, w))
+    ok = rng.random((n, h, w)) > 0.2
+    vel = rng.uniform(-20.0, 20.0, (7, 2))
+    ys, xs = rng.integers(0, h, 40), rng.integers(0, w, 40)
+    js = rng.integers(-1, 8, 40)
+    full = lc.light_curves(psi, phi, ok, t, vel, ys, xs, js)
+    at = lc.light_curves_at(lambda i, yy, xx: (psi[i, yy, xx], phi[i, yy, xx], ok[i, yy, xx]),
+                            n, h, w, t, vel, ys, xs, js)
+    for a, b in zip(full, at):
+        np.testing.assert_array_equal(a, b)
