@@ -75,27 +75,6 @@ struct BatchJob {
 
 kb_status launch_status(const char *what);
 
-// Host helpers shared by the entry points (kbmi_kernels.hip).
-// Frame limits common to every kernel: 1 <= n_img <= 32767, h <= 2^30, w <= 2^27.
-kb_status check_frame(int64_t n_img, int64_t h, int64_t w);
-// Asynchronous host-to-device copy through a pinned staging buffer (the call
-// does not wait for its stream).
-kb_status staged_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
-// Send tau_i = t_i - t_0 (double [n_img], at the workspace start) and the
-// velocities (double2 [n_vel], at byte offset *vel_off, 16-byte aligned) to
-// the workspace, for kernels that compute displacements on the device.
-kb_status upload_tau_vel(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
-                         void *workspace, hipStream_t stream, size_t *vel_off);
-
-// One displacement on the device: floor(v * tau + 0.5) as a separate IEEE
-// double multiply, add and floor (no contraction), clamped to [-lim, lim],
-// which rounds exactly as the host table does.
-__device__ inline int displacement(double v, double tau, int lim) {
-#pragma clang fp contract(off)
-    const double f = floor(v * tau + 0.5);
-    return (int)fmin(fmax(f, -(double)lim), (double)lim);
-}
-
 // Search launchers, one translation unit per plane format; km is the (even)
 // compiled list length >= k_cand.
 kb_status launch_search_f32(int km, const StackView &v, hipStream_t s);

@@ -25,7 +25,7 @@
 #include <cmath>
 #include <cstdint>
 
-#include "kbmi_device.h"
+#include "kbmi_common.h"
 
 namespace kbmi {
 namespace {

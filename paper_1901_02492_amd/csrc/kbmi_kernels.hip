@@ -23,6 +23,7 @@
 #include <mutex>
 #include <vector>
 
+#include "kbmi_common.h"
 #include "kbmi_device.h"
 
 
