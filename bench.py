@@ -68,11 +68,16 @@ def make_stack(workload):
         return synth.survey_stack()
     if workload == "small":
         return synth.small_stack()
+    if workload == "hits":
+        return synth.hits_stack()
     raise SystemExit(f"unknown workload {workload}")
 
 
 # --- CPU baseline: the FP64 oracle on crops of the same stack ---------------
 _CPU_STACK = None
+
+
+_CPU_BRIGHT = None
 
 
 def _oracle_crop(arg):
@@ -81,14 +86,19 @@ def _oracle_crop(arg):
     s = _CPU_STACK
     sl = (slice(None), slice(y0, y0 + c), slice(x0, x0 + c))
     t0 = time.perf_counter()
-    oracle.search(s.img[sl], s.var[sl], s.mask[sl], s.t, s.psf, s.vel, s.k)
+    mask = s.mask[sl]
+    if _CPU_BRIGHT is not None:
+        mask = oracle.bright_mask(s.img[sl], mask, _CPU_BRIGHT)
+    oracle.search(s.img[sl], s.var[sl], mask, s.t, s.psf, s.vel, s.k)
     return time.perf_counter() - t0
 
 
-def cpu_baseline(s, crop=224):
-    """Run the oracle on one crop per worker process (all images, all velocities)."""
-    global _CPU_STACK
+def cpu_baseline(s, crop=224, bright=None):
+    """Run the oracle on one crop per worker process (all images, all
+    velocities; the bright-pixel mask first when a level is given)."""
+    global _CPU_STACK, _CPU_BRIGHT
     _CPU_STACK = s
+    _CPU_BRIGHT = bright
     n, h, w = s.img.shape
     workers = max(1, min(16, os.cpu_count() or 1))
     c = min(crop, h, w)
@@ -114,7 +124,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="survey",
-                    choices=["survey", "small", "serve", "large", "lcfilter"])
+                    choices=["survey", "small", "serve", "large", "lcfilter", "hits"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=None,
                     help="serve: number of requests (default 200); large: per precision (default 6)")
@@ -151,9 +161,14 @@ def main():
     nv = s.vel.shape[0]
     log(f"workload {s.name}: generated in {time.perf_counter() - t0:.1f} s")
 
+    bright = None
+    if args.workload == "hits":
+        from paper_1901_02492_amd import synth
+        bright = synth.HITS_BRIGHT_SIGMA
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(s)
+        # Crops small enough that the oracle's [V][crop][crop] arrays stay modest.
+        cpu = cpu_baseline(s, crop=224 if nv <= 2000 else 32, bright=bright)
         log(f"cpu baseline {cpu['value']:.3e} TIE/s on {cpu['cores']} cores")
 
     import torch
@@ -172,6 +187,8 @@ def main():
     log("inputs resident on the device")
 
     def step(ev=None):
+        if bright is not None:
+            lib.mask_bright(img, mask, bright)
         lib.make_psi_phi(img, var, mask, s.psf, out=planes)
         if ev is not None:
             ev[0].record(stream)
@@ -214,7 +231,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": s.name, "n_img": n, "h": h, "w": w, "n_vel": nv, "k": s.k,
                    "trajectories": h * w * nv, "tie_per_step": tie,
-                   "step": "kb_make_psi_phi + kb_search + kb_topk"},
+                   "step": ("kb_mask_bright + " if bright is not None else "")
+                           + "kb_make_psi_phi + kb_search + kb_topk",
+                   "bright_threshold": bright},
         "roofline": {"bound": "hbm", "kernel": "search_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "search_ms": search_ms,

@@ -9,6 +9,8 @@
  *                     coadd, Sec. 2.2) and keep the k_cand best per start pixel
  *   kb_topk           order each start pixel's candidates and keep k
  *   kb_displacements  the integer pixel offsets every kernel uses   (Sec. 2.2)
+ * one optional stage before it:
+ *   kb_mask_bright    mask pixels above a count level           (Sec. 5.2)
  * and one stage after it:
  *   kb_lightcurve_filter  drop outlying observations from each candidate's
  *                     light curve and refit nu, alpha           (Sec. 3.3)
@@ -128,6 +130,20 @@ kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mas
                           const float *psf, int64_t psf_h, int64_t psf_w,
                           float *psi_phi, int32_t lp_dtype, void *psi_phi_lp,
                           float *lp_scale, void *stream);
+
+/*
+ * kb_mask_bright - the bright-pixel mask applied before the planes are built
+ * (Sec. 5.2, the additional mask of pixels above a fixed count level): every
+ * pixel of every image whose value exceeds `threshold` is masked in that
+ * image, mask[i][y][x] |= (img[i][y][x] > threshold).  A pixel equal to the
+ * threshold, or NaN, is left as it was.  Masked pixels then carry no weight
+ * in kb_make_psi_phi.
+ *   img   device, float32 [n_img][h][w].
+ *   mask  device, uint8 [n_img][h][w], updated in place (bit 0 is set).
+ * Errors: KB_EINVAL for null pointers, bad sizes or a NaN threshold.
+ */
+kb_status kb_mask_bright(const float *img, uint8_t *mask, int64_t n_img, int64_t h, int64_t w,
+                         float threshold, void *stream);
 
 /* Bytes of device workspace kb_search and kb_topk need for a stack of n_img
  * frames of h x w and n_vel velocities (displacement table, visiting order,

@@ -37,10 +37,20 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "validity", "weights", "psi_phi", "psi_phi_at", "displacements",
+    "bright_mask", "validity", "weights", "psi_phi", "psi_phi_at", "displacements",
     "trajectory_sums", "trajectory_sums_at", "scores", "rank_topk", "search",
     "search_rows", "search_pixels",
 ]
+
+
+def bright_mask(img, mask, threshold) -> np.ndarray:
+    """The bright-pixel mask applied before the search (Sec. 5.2): a pixel of
+    an image whose value exceeds the count threshold is masked in that image.
+    Returns uint8 [N][H][W]: the given mask with bit 0 set where img > threshold
+    (a value equal to the threshold, or NaN, does not exceed it)."""
+    img = np.asarray(img)
+    m = np.zeros(img.shape, dtype=np.uint8) if mask is None else np.array(mask, dtype=np.uint8)
+    return np.where(img > threshold, m | np.uint8(1), m).astype(np.uint8)
 
 
 def validity(img, var, mask) -> np.ndarray:

@@ -30,6 +30,7 @@ _SIGNATURES = {
     "kb_make_psi_phi": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _p, _i64, _i64, _p, _i32,
                                        _p, _p, _p]),
     "kb_search_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64]),
+    "kb_mask_bright": (ctypes.c_int, [_p, _p, _i64, _i64, _i64, ctypes.c_float, _p]),
     "kb_search": (ctypes.c_int, [_p, _i32, _p, _i64, _i64, _i64, _p, _p, _i64, _i64, _p, _p, _p,
                                  _p, _p, _sz, _p]),
     "kb_topk": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64,
@@ -132,6 +133,17 @@ _LP = {"f16": KB_F16, "bf16": KB_BF16}
 def _lp_torch_dtype(code):
     torch = _torch()
     return torch.float16 if code == KB_F16 else torch.bfloat16
+
+
+def mask_bright(img, mask, threshold, stream=None):
+    """kb_mask_bright: mask |= img > threshold, in place; returns mask."""
+    torch = _torch()
+    n, h, w = img.shape
+    if tuple(mask.shape) != (n, h, w):
+        raise ValueError("mask must have the image stack's shape")
+    _check(load().kb_mask_bright(_dev(img, torch.float32, "img"), _dev(mask, torch.uint8, "mask"),
+                                 n, h, w, float(threshold), _stream(stream)))
+    return mask
 
 
 def make_psi_phi(img, var, mask, psf, out=None, stream=None, lp=None, lp_out=None,

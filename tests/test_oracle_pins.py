@@ -366,3 +366,38 @@ def test_small_workload_top_result_at_true_track():
     r = oracle.search(s.img, s.var, s.mask, s.t, s.psf, s.vel, s.k)
     assert tuple(s.vel[r["vel"][30, 20, 0]]) == (40.0, 20.0)
     assert r["nu"][30, 20, 0] > 20
+
+
+def test_bright_mask_definition():
+    """Sec. 5.2: pixels above the count level are masked in their own image;
+    a value equal to the level, or NaN, is not above it."""
+    img = np.array([[[119.0, 120.0, 120.5], [np.nan, np.inf, -np.inf]],
+                    [[121.0, 0.0, 500.0], [120.0, 119.9, 1e30]]], dtype=np.float32)
+    mask = np.array([[[0, 4, 0], [2, 0, 0]], [[0, 0, 8], [0, 1, 0]]], dtype=np.uint8)
+    got = oracle.bright_mask(img, mask, 120.0)
+    want = np.array([[[0, 4, 1], [2, 1, 0]], [[1, 0, 9], [0, 1, 1]]], dtype=np.uint8)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(oracle.bright_mask(img, None, 120.0), (img > 120.0).astype(np.uint8))
+
+
+def test_bright_mask_removes_a_single_image_flash():
+    """A bright flash in one image makes trajectories through it the best of
+    their start pixel; masking bright pixels takes that image's term away."""
+    from paper_1901_02492_amd import synth
+    s = synth.small_stack()
+    img = s.img.copy()
+    synth.render_point_source(img[3], 40.0, 12.0, 400.0, 1.0)   # peak ~ 60 sigma
+    ref = oracle.search(img, s.var, s.mask, s.t, s.psf, s.vel, 1)
+    m = oracle.bright_mask(img, s.mask, 10.0)
+    assert m[3].sum() > 0 and m[[0, 1, 2, 4]].sum() == 0
+    cleaned = oracle.search(img, s.var, m, s.t, s.psf, s.vel, 1)
+    d = oracle.displacements(s.t, s.vel)
+    hit = 0
+    for j in range(s.vel.shape[0]):
+        y0, x0 = 12 - d[j, 3, 1], 40 - d[j, 3, 0]
+        if 0 <= y0 < 64 and 0 <= x0 < 64 and ref["vel"][y0, x0, 0] == j:
+            hit += 1
+            assert ref["nu"][y0, x0, 0] > 10.0
+            assert cleaned["all_nu"][j, y0, x0] < ref["nu"][y0, x0, 0] - 5.0
+            assert cleaned["all_nobs"][j, y0, x0] < ref["all_nobs"][j, y0, x0]
+    assert hit > 10
