@@ -135,3 +135,37 @@ def test_single_pass_clip_is_caught(monkeypatch):
         return obs & (lcf.residual_ratio(lc_psi, lc_phi, obs, J, H) > sigma_cut ** 2)
     monkeypatch.setattr(lcf, "clip", one_pass)
     assert _fails(lcpins.test_planted_outlier_is_the_only_rejection)
+
+
+# Threshold mode and clustering.
+
+from oracle import cluster as ocl  # noqa: E402
+from tests import test_oracle_cluster as clpins  # noqa: E402
+
+
+def test_unscaled_velocity_distance_is_caught(monkeypatch):
+    orig = ocl.features
+    monkeypatch.setattr(ocl, "features", lambda xs, ys, js, vel, s: orig(xs, ys, js, vel, 1.0))
+    assert _fails(clpins.test_groups_equal_sklearn_dbscan_min_samples_1, 0) or \
+        _fails(clpins.test_chains_join_and_gaps_split)
+
+
+def test_groups_without_transitivity_are_caught(monkeypatch):
+    # Label each hit by its smallest direct neighbour only (no chaining).
+    def direct(adj):
+        return np.array([int(np.nonzero(adj[i])[0].min()) for i in range(adj.shape[0])])
+    monkeypatch.setattr(ocl, "components", direct)
+    assert _fails(clpins.test_chains_join_and_gaps_split)
+
+
+def test_ties_to_the_largest_index_are_caught(monkeypatch):
+    def rev(labels, nu32, xs, ys, js):
+        best = {}
+        for i in range(labels.size):
+            key = (-float(nu32[i]), -int(ys[i]), -int(xs[i]), -int(js[i]))
+            lab = int(labels[i])
+            if lab not in best or key < best[lab][0]:
+                best[lab] = (key, i)
+        return np.array([best[int(labels[i])][1] for i in range(labels.size)])
+    monkeypatch.setattr(ocl, "representatives", rev)
+    assert _fails(clpins.test_representative_is_best_nu_with_ordered_ties)
