@@ -124,7 +124,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="survey",
-                    choices=["survey", "small", "serve", "large", "lcfilter", "hits"])
+                    choices=["survey", "small", "serve", "large", "lcfilter", "hits",
+                             "threshold"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=None,
                     help="serve: number of requests (default 200); large: per precision (default 6)")
@@ -154,6 +155,8 @@ def main():
         return serve_bench(args)
     if args.workload == "lcfilter":
         return lcfilter_bench(args)
+    if args.workload == "threshold":
+        return threshold_bench(args)
 
     t0 = time.perf_counter()
     s = make_stack(args.workload)
@@ -352,6 +355,98 @@ def lcfilter_bench(args):
         "roofline": {"bound": "hbm", "kernel": "lightcurve_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "kernel_ms": kern_ms, "bytes_per_candidate": bytes_per_cand},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# --- Threshold mode and clustering ---------------------------------------------
+TH_NU_MIN = 10.0          # Sec. 3.2
+TH_EPS = 4.0              # clustering radius (pixels) over (x, y, s*vx, s*vy)
+TH_MAX_HITS = 1 << 22
+
+
+def threshold_bench(args):
+    """Planes, the threshold search (nu >= 10) and the clustering of its hits
+    on the survey stack."""
+    s = make_stack("survey")
+    n, h, w = s.img.shape
+    nv = s.vel.shape[0]
+    log(f"workload {s.name}: generated")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(s)
+        cpu["sample"] += "; the oracle scores every trajectory, from which hits are read"
+        log(f"cpu baseline {cpu['value']:.3e} TIE/s on {cpu['cores']} cores")
+    import torch
+    from paper_1901_02492_amd import lib
+    lib.load()
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(s.img).to(dev)
+    var = torch.from_numpy(s.var).to(dev)
+    mask = torch.from_numpy(s.mask).to(dev)
+    planes = torch.empty((n, h, w, 2), dtype=torch.float32, device=dev)
+    ws = lib.alloc_workspace(n, h, w, nv, dev)
+    hits = lib.alloc_hits(TH_MAX_HITS, dev)
+    span = float(s.t[-1] - s.t[0])
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        lib.make_psi_phi(img, var, mask, s.psf, out=planes)
+        if ev is not None:
+            ev[0].record(stream)
+        cnt = lib.search_threshold(planes, s.t, s.vel, TH_NU_MIN, hits, workspace=ws)
+        if ev is not None:
+            ev[1].record(stream)
+        # The hit count decides the clustering launch: one device-to-host read.
+        nh = min(int(cnt.item()), TH_MAX_HITS)
+        if ev is not None:
+            ev[2].record(stream)
+        rep = lib.cluster_hits(hits, nh, s.vel, span, TH_EPS)
+        if ev is not None:
+            ev[3].record(stream)
+        return nh, rep
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        nh, rep = step(e)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    search_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    cluster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    groups = int(torch.unique(rep).numel()) if nh else 0
+    log(f"{args.steps} timed steps: {ms_step:.2f} ms/step, threshold search {search_ms:.2f} ms, "
+        f"{nh} hits, clustering {cluster_ms:.2f} ms, {groups} groups")
+    tie = s.tie
+    achieved = BYTES_PER_TIE_F32 * tie / (search_ms * 1e-3) / 1e9
+    line = {
+        "metric": "trajectory-image evals/s",
+        "value": tie / (ms_step * 1e-3),
+        "unit": "trajectory-image evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name}: threshold mode nu >= {TH_NU_MIN:g} and clustering "
+                               f"(eps {TH_EPS:g} px, s = {span:g} d)",
+                   "n_img": n, "h": h, "w": w, "n_vel": nv, "tie_per_step": tie,
+                   "hits": nh, "groups": groups, "cluster_ms": cluster_ms,
+                   "step": "kb_make_psi_phi + kb_search_threshold + kb_cluster_hits"},
+        "roofline": {"bound": "hbm", "kernel": "search_threshold_kernel", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "search_ms": search_ms,
+                     "bytes_per_tie": BYTES_PER_TIE_F32},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -11,7 +11,10 @@
  *   kb_displacements  the integer pixel offsets every kernel uses   (Sec. 2.2)
  * one optional stage before it:
  *   kb_mask_bright    mask pixels above a count level           (Sec. 5.2)
- * and one stage after it:
+ * a threshold mode of the search and its duplicate clustering:
+ *   kb_search_threshold   every trajectory with nu >= nu_min     (Sec. 2.2)
+ *   kb_cluster_hits   group near-identical hits, keep the best  (Sec. 3.3)
+ * and one stage after the search:
  *   kb_lightcurve_filter  drop outlying observations from each candidate's
  *                     light curve and refit nu, alpha           (Sec. 3.3)
  *
@@ -262,6 +265,69 @@ kb_status kb_lightcurve_filter(const float *psi_phi, int64_t n_img, int64_t h, i
                                const int32_t *cand_vel, int64_t k, double sigma_cut, double q,
                                float *nu, float *alpha, int16_t *nobs, uint64_t *rejected,
                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* One trajectory kept by kb_search_threshold (24 bytes). */
+typedef struct kb_hit {
+    int32_t x, y;       /* start pixel in image 0 */
+    int32_t vel;        /* velocity index */
+    float nu, alpha;    /* scores, bitwise the values kb_search gives it */
+    int16_t nobs;       /* n_obs */
+    int16_t reserved;   /* 0 */
+} kb_hit;
+
+/*
+ * kb_search_threshold - threshold mode of the search (Sec. 2.2; Sec. 3.2
+ * keeps every trajectory with nu >= 10): every (start pixel, velocity) whose
+ * nu >= nu_min is appended to `hits`, with the coadd and scores of kb_search
+ * (same sums in image order, same float32 score arithmetic).
+ *   psi_phi    device, float32 [n_img][h][w][2] planes; h, w < 2^24.
+ *   t, vel     host, as for kb_displacements.
+ *   nu_min     finite threshold.
+ *   hits       device out, kb_hit [max_hits]; the order of the hits is
+ *              unspecified (slots are reserved by atomics).
+ *   n_hits     device out, uint64: the number of trajectories with
+ *              nu >= nu_min, also when it exceeds max_hits; then only
+ *              max_hits of them, an unspecified subset, are stored, and the
+ *              call can be repeated with a larger list.
+ *   workspace  device, 256-byte aligned, >= kb_search_workspace_bytes(...).
+ * Errors: KB_EINVAL for null pointers, bad sizes, times or velocities, a
+ * non-finite threshold or a negative max_hits; KB_ENOMEM for a short
+ * workspace; KB_EUNSUPPORTED for frames of 2^24 or more on a side.
+ */
+kb_status kb_search_threshold(const float *psi_phi, int64_t n_img, int64_t h, int64_t w,
+                              const double *t, const double *vel, int64_t n_vel, float nu_min,
+                              kb_hit *hits, int64_t max_hits, uint64_t *n_hits, void *workspace,
+                              size_t workspace_bytes, void *stream);
+
+/* Device workspace bytes kb_cluster_hits needs (0 for invalid sizes). */
+size_t kb_cluster_workspace_bytes(int64_t n_hits, int64_t n_vel);
+
+/*
+ * kb_cluster_hits - duplicate clustering of kept trajectories (Sec. 3.3, last
+ * paragraph: similar (x, y, vx, vy) are grouped with DBSCAN and the most
+ * likely of each group is kept).  Reading: DBSCAN with min_samples = 1, so
+ * the groups are the connected components of the graph joining hits a, b with
+ *     ((dx*dx + dy*dy) + du*du) + dv*dv <= eps*eps     (IEEE double, in order)
+ *     dx = x_a - x_b, dy = y_a - y_b, du = s*vx_a - s*vx_b, dv = s*vy_a - s*vy_b,
+ * i.e. Euclidean distance over (x, y, s*vx, s*vy) with the velocity scaled by
+ * a time s (days).  Each group's representative is its hit with the largest
+ * nu, ties to the smallest (y, x, vel); the result does not depend on the
+ * order of `hits`.
+ *   hits    device, kb_hit [n_hits] (e.g. kb_search_threshold's list), at
+ *           most 256 * 65535 hits, distinct trajectories; a hit whose vel is
+ *           outside [0, n_vel) forms a group of its own.
+ *   vel     host, float64 [n_vel][2], the grid the hits index.
+ *   rep     device out, int32 [n_hits]: index in `hits` of each hit's group
+ *           representative (rep[i] == i for representatives).
+ *   workspace  device, 256-byte aligned, >= kb_cluster_workspace_bytes.
+ * The pair test is O(n_hits^2) (tiles of 256 x 256 hits).
+ * Errors: KB_EINVAL for null pointers, bad sizes or velocities, s or eps not
+ * finite and >= 0; KB_ENOMEM for a short workspace; KB_EUNSUPPORTED for more
+ * hits than one launch covers.
+ */
+kb_status kb_cluster_hits(const kb_hit *hits, int64_t n_hits, const double *vel, int64_t n_vel,
+                          double s, double eps, int32_t *rep, void *workspace,
+                          size_t workspace_bytes, void *stream);
 
 /*
  * Batched search (serving).  One stack of a batch: the kb_search arguments of

@@ -51,7 +51,10 @@ def build_library(verbose: bool = False, out: str = LIB, defines=(), jobs: int =
                  ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_kernels.hip"),
                    "-o", os.path.join(tmp, "kbmi_kernels.o")], os.path.join(tmp, "kbmi_kernels.o")),
                  ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_filter.hip"),
-                   "-o", os.path.join(tmp, "kbmi_filter.o")], os.path.join(tmp, "kbmi_filter.o"))]
+                   "-o", os.path.join(tmp, "kbmi_filter.o")], os.path.join(tmp, "kbmi_filter.o")),
+                 ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_threshold.hip"),
+                   "-o", os.path.join(tmp, "kbmi_threshold.o")],
+                  os.path.join(tmp, "kbmi_threshold.o"))]
         for fmt in (0, 1, 2):
             obj = os.path.join(tmp, f"kbmi_search_{fmt}.o")
             steps.append(([HIPCC, *DEVICE_FLAGS, *dflags, f"-DKBMI_FMT={fmt}", "-c",

@@ -25,6 +25,12 @@ kb_status staged_copy(void *dst, const void *src, size_t bytes, hipStream_t stre
 // the workspace, for kernels that compute displacements on the device.
 kb_status upload_tau_vel(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                          void *workspace, hipStream_t stream, size_t *vel_off);
+// Send the gather table (planes of `pix_bytes` bytes per pair; velocities in
+// visiting order unless visiting_order is false) and the visiting order to
+// the workspace (workspace_layout offsets).
+kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+                       int64_t h, int64_t w, int64_t pix_bytes, void *workspace,
+                       hipStream_t stream, bool visiting_order = true);
 
 // One displacement on the device: floor(v * tau + 0.5) as a separate IEEE
 // double multiply, add and floor (no contraction), clamped to [-lim, lim],

@@ -491,13 +491,11 @@ kb_status upload_tau_vel(const double *t, int64_t n_img, const double *vel, int6
     return staged_copy(workspace, staged.data(), staged.size(), stream);
 }
 
-namespace {
-
 // Copy the gather table (for planes of `pix_bytes` bytes per pair) and the
 // visiting order into the workspace, asynchronously on `stream`.
 kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                        int64_t h, int64_t w, int64_t pix_bytes, void *workspace,
-                       hipStream_t stream, bool visiting_order = true) {
+                       hipStream_t stream, bool visiting_order) {
     const size_t tb = table_bytes(n_img, n_vel);
     std::vector<char> host(tb + static_cast<size_t>(n_vel) * sizeof(int32_t));
     gather_table(t, n_img, vel, n_vel, h, w, pix_bytes, visiting_order,
@@ -507,7 +505,6 @@ kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_
     return staged_copy(workspace, host.data(), host.size(), stream);
 }
 
-}  // namespace
 }  // namespace kbmi
 
 using namespace kbmi;

@@ -38,6 +38,11 @@ _SIGNATURES = {
     "kb_lightcurve_filter": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, _p, _i64,
                                             ctypes.c_double, ctypes.c_double, _p, _p, _p, _p, _p,
                                             _sz, _p]),
+    "kb_search_threshold": (ctypes.c_int, [_p, _i64, _i64, _i64, _p, _p, _i64, ctypes.c_float,
+                                           _p, _i64, _p, _p, _sz, _p]),
+    "kb_cluster_workspace_bytes": (_sz, [_i64, _i64]),
+    "kb_cluster_hits": (ctypes.c_int, [_p, _i64, _p, _i64, ctypes.c_double, ctypes.c_double, _p,
+                                       _p, _sz, _p]),
     "kb_search_batch_workspace_bytes": (_sz, [_p, _i64]),
     "kb_search_batch": (ctypes.c_int, [_p, _i64, _i32, _i64, _p, _sz, _p]),
 }
@@ -274,6 +279,61 @@ def lightcurve_filter(planes, t, vel, cand_vel, sigma_cut=5.0, q=0.0, out=None,
         _dev(no, torch.int16, "nobs"), None if rej is None else _dev(rej, torch.int64, "rejected"),
         _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)))
     return (nu, al, no, rej) if rejected else (nu, al, no)
+
+
+# Layout of the C struct kb_hit (24 bytes).
+HIT_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("vel", "<i4"), ("nu", "<f4"),
+                      ("alpha", "<f4"), ("nobs", "<i2"), ("reserved", "<i2")])
+
+
+def alloc_hits(max_hits, device):
+    """Device storage for max_hits kb_hit records (int32 [max_hits][6])."""
+    torch = _torch()
+    return torch.empty((max(int(max_hits), 1), 6), dtype=torch.int32, device=device)
+
+
+def hits_to_numpy(hits, n):
+    """The first n records of a hit list as a structured numpy array."""
+    n = int(n)
+    raw = hits[:n].contiguous().cpu().numpy()
+    return raw.view(HIT_DTYPE).reshape(n)
+
+
+def search_threshold(planes, t, vel, nu_min, hits, workspace=None, stream=None):
+    """kb_search_threshold: appends every trajectory with nu >= nu_min to
+    `hits` (from alloc_hits); returns the device counter (int64 [1]) holding
+    the total number of such trajectories."""
+    torch = _torch()
+    n, h, w, _ = planes.shape
+    t = _host_f64(t)
+    vel = _host_f64(vel, 2)
+    count = torch.empty(1, dtype=torch.int64, device=planes.device)
+    if workspace is None:
+        workspace = alloc_workspace(n, h, w, vel.shape[0], planes.device)
+    _check(load().kb_search_threshold(
+        _dev(planes, torch.float32, "psi_phi"), n, h, w, t.ctypes.data, vel.ctypes.data,
+        vel.shape[0], float(nu_min), _dev(hits, torch.int32, "hits"), hits.shape[0],
+        _dev(count, torch.int64, "n_hits"), _dev(workspace, torch.uint8, "workspace"),
+        workspace.numel(), _stream(stream)))
+    return count
+
+
+def cluster_hits(hits, n_hits, vel, s, eps, workspace=None, stream=None):
+    """kb_cluster_hits over the first n_hits records: int32 [n_hits] index of
+    each hit's group representative."""
+    torch = _torch()
+    vel = _host_f64(vel, 2)
+    n_hits = int(n_hits)
+    rep = torch.empty(max(n_hits, 1), dtype=torch.int32, device=hits.device)
+    if workspace is None:
+        nb = load().kb_cluster_workspace_bytes(n_hits, vel.shape[0])
+        workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=hits.device)
+    _check(load().kb_cluster_hits(_dev(hits, torch.int32, "hits"), n_hits, vel.ctypes.data,
+                                  vel.shape[0], float(s), float(eps),
+                                  _dev(rep, torch.int32, "rep"),
+                                  _dev(workspace, torch.uint8, "workspace"), workspace.numel(),
+                                  _stream(stream)))
+    return rep[:n_hits]
 
 
 def _job_array(jobs):

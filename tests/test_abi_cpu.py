@@ -205,3 +205,36 @@ def test_lightcurve_filter_argument_checks():
     assert st == lib.KB_ENOMEM and "workspace" in msg
     st, msg = _lc_call(t=np.array([0.0, 2.0, 1.0]))
     assert st == lib.KB_EINVAL and "non-decreasing" in msg
+
+
+def test_threshold_and_cluster_argument_checks():
+    L = lib.load()
+    fake = 1 << 20
+    t = np.arange(3, dtype=np.float64)
+    v = np.zeros((4, 2))
+    call = lambda **kw: L.kb_search_threshold(
+        fake, 3, kw.get("h", 8), kw.get("w", 8), t.ctypes.data, v.ctypes.data, kw.get("nv", 4),
+        kw.get("m", 10.0), kw.get("hits", fake), kw.get("cap", 16), kw.get("cnt", fake),
+        kw.get("ws", fake), kw.get("wsb", 1 << 20), None)
+    assert call(m=float("nan")) == lib.KB_EINVAL
+    assert call(m=float("inf")) == lib.KB_EINVAL
+    assert call(cnt=None) == lib.KB_EINVAL
+    assert call(cap=-1) == lib.KB_EINVAL
+    assert call(hits=None) == lib.KB_EINVAL
+    assert call(w=1 << 24) == lib.KB_EUNSUPPORTED
+    assert call(wsb=64) == lib.KB_ENOMEM
+    assert call(nv=0) == lib.KB_EINVAL
+    vv = np.zeros((4, 2))
+    cl = lambda **kw: L.kb_cluster_hits(kw.get("hits", fake), kw.get("n", 10), vv.ctypes.data,
+                                        4, kw.get("s", 1.0), kw.get("eps", 2.0),
+                                        kw.get("rep", fake), kw.get("ws", fake),
+                                        kw.get("wsb", 1 << 20), None)
+    assert cl(n=0, hits=None) == lib.KB_OK          # nothing to do
+    assert cl(n=-1) == lib.KB_EINVAL
+    assert cl(eps=-1.0) == lib.KB_EINVAL
+    assert cl(s=float("nan")) == lib.KB_EINVAL
+    assert cl(rep=None) == lib.KB_EINVAL
+    assert cl(wsb=16) == lib.KB_ENOMEM
+    assert cl(n=256 * 65535 + 1) == lib.KB_EUNSUPPORTED
+    assert L.kb_cluster_workspace_bytes(1000, 4) >= 1000 * 20
+    assert lib.HIT_DTYPE.itemsize == 24
