@@ -169,3 +169,39 @@ def test_ties_to_the_largest_index_are_caught(monkeypatch):
         return np.array([best[int(labels[i])][1] for i in range(labels.size)])
     monkeypatch.setattr(ocl, "representatives", rev)
     assert _fails(clpins.test_representative_is_best_nu_with_ordered_ties)
+
+
+# Stamps and moments.
+
+from oracle import stamps as ost  # noqa: E402
+from tests import test_oracle_stamps as stpins  # noqa: E402
+
+
+def test_sum_instead_of_mean_is_caught(monkeypatch):
+    orig = ost.coadd_stamps
+
+    def summed(img, var, mask, t, vel, xs, ys, js, R, keep=None):
+        S = orig(img, var, mask, t, vel, xs, ys, js, R, keep)
+        return S * np.asarray(img).shape[0]
+    monkeypatch.setattr(ost, "coadd_stamps", summed)
+    assert _fails(stpins.test_mean_over_valid_pixels)
+
+
+def test_moments_about_the_centre_not_the_centroid_are_caught(monkeypatch):
+    orig = ost.moments
+
+    def raw(S):
+        M00, ub, vb, m20, m02, m11 = orig(S)
+        return M00, ub, vb, m20 + ub * ub, m02 + vb * vb, m11 + ub * vb
+    monkeypatch.setattr(ost, "moments", raw)
+    assert _fails(stpins.test_elongated_source_fails) or \
+        _fails(stpins.test_source_beside_the_trajectory_moves_the_centroid) or \
+        _fails(stpins.test_point_source_moments_are_the_psf_variance, 1.0, 6)
+
+
+def test_ignored_keep_mask_is_caught(monkeypatch):
+    orig = ost.coadd_stamps
+    monkeypatch.setattr(ost, "coadd_stamps",
+                        lambda img, var, mask, t, vel, xs, ys, js, R, keep=None:
+                        orig(img, var, mask, t, vel, xs, ys, js, R, None))
+    assert _fails(stpins.test_excluding_the_flash_image_restores_the_point_source)
