@@ -57,6 +57,10 @@ def test_source_beside_the_trajectory_moves_the_centroid():
     S = os_.coadd_stamps(img, var, mask, t, vel, [20], [22], [0], 8)
     mom = os_.moments(S)
     assert mom[1][0] == pytest.approx(2.0, abs=1e-4) and abs(mom[2][0]) < 1e-9
+    # Central moments are taken about the centroid: the spread is the PSF's
+    # (pixel-integrated sigma = 1: variance 1 + 1/12), not 4 px^2 more.
+    assert mom[3][0] == pytest.approx(1.0 + 1.0 / 12.0, abs=1e-3)
+    assert mom[4][0] == pytest.approx(1.0 + 1.0 / 12.0, abs=1e-3)
     assert not os_.stamp_filter(mom, 1.0, 0.5, 0.5, 2.0)[0]
 
 
