@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="survey",
                     choices=["survey", "small", "serve", "large", "lcfilter", "hits",
-                             "threshold"])
+                             "threshold", "stamps"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=None,
                     help="serve: number of requests (default 200); large: per precision (default 6)")
@@ -157,6 +157,8 @@ def main():
         return lcfilter_bench(args)
     if args.workload == "threshold":
         return threshold_bench(args)
+    if args.workload == "stamps":
+        return stamps_bench(args)
 
     t0 = time.perf_counter()
     s = make_stack(args.workload)
@@ -447,6 +449,107 @@ def threshold_bench(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "search_ms": search_ms,
                      "bytes_per_tie": BYTES_PER_TIE_F32},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# --- Postage stamps -------------------------------------------------------------
+ST_RADIUS = 5
+ST_LIMITS = (1.0, 1.0, 0.5, 6.0)   # max_offset, max_m11, m2_min, m2_max (px, px^2)
+ST_REGION = 512                    # top-1 candidate of every pixel of a central region
+
+
+def stamps_cpu_baseline(s, cand, n_cand=30000):
+    """The oracle's stamps and moments for the first n_cand candidates (one process)."""
+    from oracle import stamps as ost
+    c = cand[:n_cand]
+    t0 = time.perf_counter()
+    S = ost.coadd_stamps(s.img, s.var, s.mask, s.t, s.vel, c["x"], c["y"], c["vel"], ST_RADIUS)
+    ost.stamp_filter(ost.moments(S), *ST_LIMITS)
+    wall = time.perf_counter() - t0
+    return {"value": c.size / wall, "unit": "candidates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{c.size} of the benchmark's candidates, R = {ST_RADIUS}, FP64 numpy "
+                      f"oracle in one process; wall {wall:.1f} s"}
+
+
+def stamps_bench(args):
+    """kb_stamps on the best trajectory of every start pixel of a 512 x 512
+    region of the survey stack (candidates from the GPU search, untimed)."""
+    s = make_stack("survey")
+    n, h, w = s.img.shape
+    nv = s.vel.shape[0]
+    import torch
+    from paper_1901_02492_amd import lib
+    lib.load()
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(s.img).to(dev)
+    var = torch.from_numpy(s.var).to(dev)
+    mask = torch.from_numpy(s.mask).to(dev)
+    planes, res = lib.run_search(img, var, mask, s.t, s.psf, s.vel, 1)
+    y0 = x0 = (h - ST_REGION) // 2
+    yy, xx = torch.meshgrid(torch.arange(y0, y0 + ST_REGION, device=dev),
+                            torch.arange(x0, x0 + ST_REGION, device=dev), indexing="ij")
+    cand = torch.zeros((ST_REGION * ST_REGION, 6), dtype=torch.int32, device=dev)
+    cand[:, 0] = xx.reshape(-1).to(torch.int32)
+    cand[:, 1] = yy.reshape(-1).to(torch.int32)
+    cand[:, 2] = res[2][y0:y0 + ST_REGION, x0:x0 + ST_REGION, 0].reshape(-1)
+    del planes, res
+    nc = cand.shape[0]
+    ws = lib.alloc_workspace(n, h, w, nv, dev)
+    torch.cuda.synchronize()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = stamps_cpu_baseline(s, lib.hits_to_numpy(cand, min(nc, 30000)))
+        log(f"cpu baseline {cpu['value']:.3e} candidates/s")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return lib.stamps(img, var, mask, s.t, s.vel, cand, nc, ST_RADIUS, *ST_LIMITS,
+                          workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        ok, _, _ = step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    npass = int(ok.sum().item())
+    side = 2 * ST_RADIUS + 1
+    # Algorithmic bytes per candidate: its record (12), image, variance and
+    # mask over the stamp in every image (9 per pixel), the stamp, moments and
+    # flag written.
+    per = 12 + side * side * n * 9 + side * side * 4 + 48 + 1
+    achieved = per * nc / (kern_ms * 1e-3) / 1e9
+    log(f"{args.steps} timed steps: {ms_step:.2f} ms/step, stamps call {kern_ms:.2f} ms, "
+        f"{npass} of {nc} pass")
+    line = {
+        "metric": "candidates/s",
+        "value": nc / (ms_step * 1e-3),
+        "unit": "candidates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name}: coadded {side}x{side} stamps and moment filter for "
+                               f"the best trajectory of every pixel of a {ST_REGION}^2 region",
+                   "n_img": n, "candidates": nc, "radius": ST_RADIUS, "limits": ST_LIMITS,
+                   "passed": npass, "step": "kb_stamps"},
+        "roofline": {"bound": "hbm", "kernel": "stamp_kernel", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "kernel_ms": kern_ms, "bytes_per_candidate": per},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -14,9 +14,10 @@
  * a threshold mode of the search and its duplicate clustering:
  *   kb_search_threshold   every trajectory with nu >= nu_min     (Sec. 2.2)
  *   kb_cluster_hits   group near-identical hits, keep the best  (Sec. 3.3)
- * and one stage after the search:
+ * and two stages after the search:
  *   kb_lightcurve_filter  drop outlying observations from each candidate's
  *                     light curve and refit nu, alpha           (Sec. 3.3)
+ *   kb_stamps         coadded postage stamps and moment filter  (Sec. 3.3)
  *
  * Conventions shared by every call
  *   - Pixel (x, y) is column x, row y of a row-major [h][w] frame; integer
@@ -63,6 +64,8 @@ extern "C" {
 /* Largest image count kb_lightcurve_filter accepts (one bit per image in its
  * rejection mask). */
 #define KB_MAX_LC_IMAGES 64
+/* Largest stamp radius kb_stamps accepts (stamps of (2R+1)^2 pixels). */
+#define KB_MAX_STAMP_RADIUS 15
 
 typedef enum kb_status {
     KB_OK = 0,
@@ -328,6 +331,49 @@ size_t kb_cluster_workspace_bytes(int64_t n_hits, int64_t n_vel);
 kb_status kb_cluster_hits(const kb_hit *hits, int64_t n_hits, const double *vel, int64_t n_vel,
                           double s, double eps, int32_t *rep, void *workspace,
                           size_t workspace_bytes, void *stream);
+
+/*
+ * kb_stamps - coadded postage stamps of candidate trajectories and the
+ * central-moment filter (Sec. 3.3, second paragraph; the paper names neither
+ * the coadd nor the comparison, this is the variant implemented).
+ * For candidate (x, y, vel) and offsets u, v in [-R, R]:
+ *     S(u, v) = (sum over kept images i of img_i(x_i + u, y_i + v)) / n(u, v)
+ * over the pixels inside the frame and valid (mask 0, finite image, finite
+ * positive variance), summed in image order in double; S = 0 where n = 0.
+ * (x_i, y_i) is the trajectory pixel floor(v * tau_i + 0.5) from (x, y), as
+ * in kb_displacements.  Moments in one row-major pass (v outer, u inner):
+ *     M00 = sum S, M10 = sum u S, M01 = sum v S, M20 = sum (u u) S,
+ *     M02 = sum (v v) S, M11 = sum (u v) S;
+ *     ub = M10/M00, vb = M01/M00, m20 = M20/M00 - ub ub,
+ *     m02 = M02/M00 - vb vb, m11 = M11/M00 - ub vb
+ * (separately rounded double operations).  pass = M00 > 0 and |ub|, |vb| <=
+ * max_offset and |m11| <= max_m11 and m2_min <= m20, m02 <= m2_max: the
+ * stamp resembles a Gaussian centred on it, whose centroid is 0, m11 is 0 and
+ * m20 = m02 its variance.
+ *   img, var, mask  device, [n_img][h][w] float32, float32, uint8 (mask may
+ *              be NULL: nothing masked); n_img <= KB_MAX_LC_IMAGES.
+ *   t, vel     host, as for kb_displacements.
+ *   cand       device, kb_hit [n_cand] (x, y, vel are used); a vel outside
+ *              [0, n_vel) gives an all-zero stamp, NaN moments, pass 0.
+ *   drop       device or NULL, uint64 [n_cand]: bit i set excludes image i
+ *              (e.g. the light-curve filter's rejection mask).
+ *   radius     R in [0, KB_MAX_STAMP_RADIUS].
+ *   stamps     device out or NULL, float32 [n_cand][2R+1][2R+1].
+ *   moments    device out or NULL, float64 [n_cand][6]: M00, ub, vb, m20,
+ *              m02, m11 (NaN where M00 = 0).
+ *   pass       device out, uint8 [n_cand].
+ *   workspace  device, 256-byte aligned, >= kb_search_workspace_bytes(n_img,
+ *              h, w, n_vel); tau and the velocities are copied into it.
+ * Errors: KB_EINVAL for null pointers, bad sizes, times or velocities, a bad
+ * radius or NaN bounds; KB_ENOMEM for a short workspace; KB_EUNSUPPORTED for
+ * n_img > KB_MAX_LC_IMAGES.
+ */
+kb_status kb_stamps(const float *img, const float *var, const uint8_t *mask, int64_t n_img,
+                    int64_t h, int64_t w, const double *t, const double *vel, int64_t n_vel,
+                    const kb_hit *cand, const uint64_t *drop, int64_t n_cand, int32_t radius,
+                    double max_offset, double max_m11, double m2_min, double m2_max,
+                    float *stamps, double *moments, uint8_t *pass, void *workspace,
+                    size_t workspace_bytes, void *stream);
 
 /*
  * Batched search (serving).  One stack of a batch: the kb_search arguments of

@@ -54,7 +54,9 @@ def build_library(verbose: bool = False, out: str = LIB, defines=(), jobs: int =
                    "-o", os.path.join(tmp, "kbmi_filter.o")], os.path.join(tmp, "kbmi_filter.o")),
                  ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_threshold.hip"),
                    "-o", os.path.join(tmp, "kbmi_threshold.o")],
-                  os.path.join(tmp, "kbmi_threshold.o"))]
+                  os.path.join(tmp, "kbmi_threshold.o")),
+                 ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_stamps.hip"),
+                   "-o", os.path.join(tmp, "kbmi_stamps.o")], os.path.join(tmp, "kbmi_stamps.o"))]
         for fmt in (0, 1, 2):
             obj = os.path.join(tmp, f"kbmi_search_{fmt}.o")
             steps.append(([HIPCC, *DEVICE_FLAGS, *dflags, f"-DKBMI_FMT={fmt}", "-c",

@@ -1,0 +1,200 @@
+// Coadded postage stamps and the central-moment filter of libkbmi (Sec. 3.3,
+// second paragraph: the remaining candidates' coadded stamps are kept when
+// their central moments resemble those of a Gaussian centred on the stamp).
+//
+// One thread per candidate.  Its displacements are computed once into
+// registers (floor(v * tau + 0.5) in double, as everywhere else); then, for
+// each stamp pixel in row-major order, the science-image pixels of the kept
+// images are averaged in image order in double, and the raw moments about the
+// stamp centre are accumulated in the same pass.  Every product, sum and
+// quotient is a separately rounded IEEE double operation in a fixed order, so
+// the outputs are a reproducible function of the inputs:
+//   S(u, v) = (sum_i img_i) / n(u, v)  over valid in-frame pixels (0 if none)
+//   M00 += S, M10 += u S, M01 += v S, M20 += (u u) S, M02 += (v v) S,
+//   M11 += (u v) S
+//   ub = M10/M00, vb = M01/M00, m20 = M20/M00 - ub ub, m02 = M02/M00 - vb vb,
+//   m11 = M11/M00 - ub vb
+// and the stamp passes when M00 > 0, |ub|, |vb| <= max_offset,
+// |m11| <= max_m11 and m2_min <= m20, m02 <= m2_max.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kbmi_common.h"
+
+namespace kbmi {
+namespace {
+
+constexpr int ST_THREADS = 128;
+
+// floor(v * tau + 0.5) without the clamp of the search's table: a stamp
+// reaches R pixels past its centre, so an offset beyond the frame must stay
+// exact (|v * tau| < 2^30 is checked on the host).
+__device__ inline int stamp_offset(double v, double tau) {
+#pragma clang fp contract(off)
+    return (int)floor(v * tau + 0.5);
+}
+
+struct StampLimits {
+    double max_offset, max_m11, m2_min, m2_max;
+};
+
+template <int NB>
+__global__ __launch_bounds__(ST_THREADS) void stamp_kernel(
+    const float *__restrict__ img, const float *__restrict__ var,
+    const uint8_t *__restrict__ mask, int n_img, int h, int w, const double *__restrict__ tau,
+    const double2 *__restrict__ vels, int n_vel, const kb_hit *__restrict__ cand,
+    const uint64_t *__restrict__ drop, int64_t n_cand, int R, StampLimits lim,
+    float *__restrict__ stamps, double *__restrict__ moments, uint8_t *__restrict__ pass) {
+#pragma clang fp contract(off)
+    const int64_t c = (int64_t)blockIdx.x * ST_THREADS + threadIdx.x;
+    if (c >= n_cand) return;
+    const kb_hit hit = cand[c];
+    const int side = 2 * R + 1;
+    const bool ok_vel = hit.vel >= 0 && hit.vel < n_vel;
+    int dx[NB], dy[NB];
+    uint64_t use = 0;   // images this candidate may use
+    if (ok_vel) {
+        const double2 vj = vels[hit.vel];
+        const uint64_t dropped = drop ? drop[c] : 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            dx[i] = 0;
+            dy[i] = 0;
+            if (i < n_img) {
+                dx[i] = stamp_offset(vj.x, tau[i]);
+                dy[i] = stamp_offset(vj.y, tau[i]);
+                if (!((dropped >> i) & 1u)) use |= uint64_t(1) << i;
+            }
+        }
+    }
+    double M00 = 0.0, M10 = 0.0, M01 = 0.0, M20 = 0.0, M02 = 0.0, M11 = 0.0;
+    for (int a = 0; a < side; ++a) {
+        const double v = (double)(a - R);
+        for (int b = 0; b < side; ++b) {
+            const double u = (double)(b - R);
+            double acc = 0.0;
+            int cnt = 0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                if ((use >> i) & 1u) {
+                    const int64_t yy = (int64_t)hit.y + dy[i] + (a - R);
+                    const int64_t xx = (int64_t)hit.x + dx[i] + (b - R);
+                    if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
+                        const size_t p = ((size_t)i * h + yy) * (size_t)w + xx;
+                        const float im = img[p];
+                        const float va = var[p];
+                        const bool valid = (mask == nullptr || mask[p] == 0) && isfinite(im) &&
+                                           isfinite(va) && va > 0.f;
+                        if (valid) {
+                            acc = acc + (double)im;
+                            ++cnt;
+                        }
+                    }
+                }
+            }
+            const double S = cnt > 0 ? acc / (double)cnt : 0.0;   // exact int -> double
+            if (stamps) stamps[c * side * side + a * side + b] = (float)S;
+            M00 = M00 + S;
+            M10 = M10 + u * S;
+            M01 = M01 + v * S;
+            M20 = M20 + (u * u) * S;
+            M02 = M02 + (v * v) * S;
+            M11 = M11 + (u * v) * S;
+        }
+    }
+    const double ub = M10 / M00, vb = M01 / M00;
+    const double m20 = M20 / M00 - ub * ub;
+    const double m02 = M02 / M00 - vb * vb;
+    const double m11 = M11 / M00 - ub * vb;
+    const bool ok = ok_vel && M00 > 0.0 && fabs(ub) <= lim.max_offset &&
+                    fabs(vb) <= lim.max_offset && fabs(m11) <= lim.max_m11 &&
+                    m20 >= lim.m2_min && m20 <= lim.m2_max && m02 >= lim.m2_min &&
+                    m02 <= lim.m2_max;
+    pass[c] = ok ? 1 : 0;
+    if (moments) {
+        double *o = moments + c * 6;
+        o[0] = M00;
+        o[1] = ub;
+        o[2] = vb;
+        o[3] = m20;
+        o[4] = m02;
+        o[5] = m11;
+    }
+}
+
+template <int NB>
+kb_status launch_stamps(const float *img, const float *var, const uint8_t *mask, int n_img,
+                        int h, int w, const double *tau, const double2 *vels, int n_vel,
+                        const kb_hit *cand, const uint64_t *drop, int64_t n_cand, int R,
+                        StampLimits lim, float *stamps, double *moments, uint8_t *pass,
+                        hipStream_t s) {
+    const int64_t blocks = (n_cand + ST_THREADS - 1) / ST_THREADS;
+    hipLaunchKernelGGL(stamp_kernel<NB>, dim3((unsigned)blocks), dim3(ST_THREADS), 0, s, img, var,
+                       mask, n_img, h, w, tau, vels, n_vel, cand, drop, n_cand, R, lim, stamps,
+                       moments, pass);
+    return launch_status("stamp_kernel");
+}
+
+}  // namespace
+}  // namespace kbmi
+
+using namespace kbmi;
+
+extern "C" {
+
+kb_status kb_stamps(const float *img, const float *var, const uint8_t *mask, int64_t n_img,
+                    int64_t h, int64_t w, const double *t, const double *vel, int64_t n_vel,
+                    const kb_hit *cand, const uint64_t *drop, int64_t n_cand, int32_t radius,
+                    double max_offset, double max_m11, double m2_min, double m2_max,
+                    float *stamps, double *moments, uint8_t *pass, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (n_cand < 0) return fail(KB_EINVAL, "n_cand must be >= 0");
+    if (!img || !var || !t || !vel || !pass || (n_cand > 0 && !cand))
+        return fail(KB_EINVAL, "img, var, times, velocities, candidates and pass must be non-null");
+    kb_status st = check_frame(n_img, h, w);
+    if (st != KB_OK) return st;
+    if (n_img > KB_MAX_LC_IMAGES)
+        return fail(KB_EUNSUPPORTED, "stamps take at most %d images (got %lld)",
+                    KB_MAX_LC_IMAGES, (long long)n_img);
+    if (n_vel < 1 || n_vel > 65535)
+        return fail(KB_EINVAL, "n_vel must be in [1, 65535] (got %lld)", (long long)n_vel);
+    if (radius < 0 || radius > KB_MAX_STAMP_RADIUS)
+        return fail(KB_EINVAL, "radius must be in [0, %d] (got %d)", KB_MAX_STAMP_RADIUS,
+                    (int)radius);
+    if (std::isnan(max_offset) || std::isnan(max_m11) || std::isnan(m2_min) || std::isnan(m2_max))
+        return fail(KB_EINVAL, "filter bounds must not be NaN");
+    if (n_cand > (int64_t)ST_THREADS * 2147483647LL)
+        return fail(KB_EINVAL, "too many candidates for one launch");
+    st = check_times_velocities(t, n_img, vel, n_vel);
+    if (st != KB_OK) return st;
+    if (!workspace) return fail(KB_EINVAL, "stamps need a workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(KB_EINVAL, "workspace must be 256-byte aligned");
+    const size_t ws_need = workspace_layout(n_img, h, w, n_vel).total;
+    if (workspace_bytes < ws_need)
+        return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need, workspace_bytes);
+    if (n_cand == 0) return KB_OK;
+    hipStream_t s = (hipStream_t)stream;
+    size_t vel_off = 0;
+    st = upload_tau_vel(t, n_img, vel, n_vel, workspace, s, &vel_off);
+    if (st != KB_OK) return st;
+    const char *ws = static_cast<const char *>(workspace);
+    const double *tau = reinterpret_cast<const double *>(ws);
+    const double2 *vels = reinterpret_cast<const double2 *>(ws + vel_off);
+    const StampLimits lim{max_offset, max_m11, m2_min, m2_max};
+    if (n_img <= 16)
+        return launch_stamps<16>(img, var, mask, (int)n_img, (int)h, (int)w, tau, vels,
+                                 (int)n_vel, cand, drop, n_cand, radius, lim, stamps, moments,
+                                 pass, s);
+    if (n_img <= 32)
+        return launch_stamps<32>(img, var, mask, (int)n_img, (int)h, (int)w, tau, vels,
+                                 (int)n_vel, cand, drop, n_cand, radius, lim, stamps, moments,
+                                 pass, s);
+    return launch_stamps<64>(img, var, mask, (int)n_img, (int)h, (int)w, tau, vels, (int)n_vel,
+                             cand, drop, n_cand, radius, lim, stamps, moments, pass, s);
+}
+
+}  // extern "C"

@@ -43,6 +43,9 @@ _SIGNATURES = {
     "kb_cluster_workspace_bytes": (_sz, [_i64, _i64]),
     "kb_cluster_hits": (ctypes.c_int, [_p, _i64, _p, _i64, ctypes.c_double, ctypes.c_double, _p,
                                        _p, _sz, _p]),
+    "kb_stamps": (ctypes.c_int, [_p, _p, _p, _i64, _i64, _i64, _p, _p, _i64, _p, _p, _i64,
+                                 ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, _p, _p, _p, _p, _sz, _p]),
     "kb_search_batch_workspace_bytes": (_sz, [_p, _i64]),
     "kb_search_batch": (ctypes.c_int, [_p, _i64, _i32, _i64, _p, _sz, _p]),
 }
@@ -334,6 +337,36 @@ def cluster_hits(hits, n_hits, vel, s, eps, workspace=None, stream=None):
                                   _dev(workspace, torch.uint8, "workspace"), workspace.numel(),
                                   _stream(stream)))
     return rep[:n_hits]
+
+
+def stamps(img, var, mask, t, vel, cand, n_cand, radius, max_offset, max_m11, m2_min, m2_max,
+           drop=None, want_stamps=True, workspace=None, stream=None):
+    """kb_stamps over the first n_cand records of `cand` (kb_hit list):
+    returns (pass uint8 [n], moments float64 [n][6], stamps float32
+    [n][2R+1][2R+1] or None)."""
+    torch = _torch()
+    n, h, w = img.shape
+    t = _host_f64(t)
+    vel = _host_f64(vel, 2)
+    n_cand = int(n_cand)
+    dev = img.device
+    side = 2 * int(radius) + 1
+    ok = torch.empty(max(n_cand, 1), dtype=torch.uint8, device=dev)
+    mom = torch.empty((max(n_cand, 1), 6), dtype=torch.float64, device=dev)
+    st = (torch.empty((max(n_cand, 1), side, side), dtype=torch.float32, device=dev)
+          if want_stamps else None)
+    if workspace is None:
+        workspace = alloc_workspace(n, h, w, vel.shape[0], dev)
+    _check(load().kb_stamps(
+        _dev(img, torch.float32, "img"), _dev(var, torch.float32, "var"),
+        None if mask is None else _dev(mask, torch.uint8, "mask"), n, h, w, t.ctypes.data,
+        vel.ctypes.data, vel.shape[0], _dev(cand, torch.int32, "cand"),
+        None if drop is None else _dev(drop, torch.int64, "drop"), n_cand, int(radius),
+        float(max_offset), float(max_m11), float(m2_min), float(m2_max),
+        None if st is None else _dev(st, torch.float32, "stamps"),
+        _dev(mom, torch.float64, "moments"), _dev(ok, torch.uint8, "pass"),
+        _dev(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream)))
+    return ok[:n_cand], mom[:n_cand], (None if st is None else st[:n_cand])
 
 
 def _job_array(jobs):

@@ -238,3 +238,25 @@ def test_threshold_and_cluster_argument_checks():
     assert cl(n=256 * 65535 + 1) == lib.KB_EUNSUPPORTED
     assert L.kb_cluster_workspace_bytes(1000, 4) >= 1000 * 20
     assert lib.HIT_DTYPE.itemsize == 24
+
+
+def test_stamps_argument_checks():
+    L = lib.load()
+    fake = 1 << 20
+    t = np.arange(3, dtype=np.float64)
+    v = np.zeros((4, 2))
+    call = lambda **kw: L.kb_stamps(
+        fake, fake, None, kw.get("n", 3), 8, 8, t.ctypes.data if kw.get("n", 3) == 3 else
+        np.arange(kw["n"], dtype=np.float64).ctypes.data, v.ctypes.data, 4, fake, None,
+        kw.get("nc", 5), kw.get("R", 2), kw.get("off", 1.0), 1.0, 0.5, 4.0, None, None,
+        kw.get("ok", fake), fake, kw.get("wsb", 1 << 20), None)
+    assert call(R=-1) == lib.KB_EINVAL
+    assert call(R=16) == lib.KB_EINVAL
+    assert call(off=float("nan")) == lib.KB_EINVAL
+    assert call(ok=None) == lib.KB_EINVAL
+    assert call(nc=-1) == lib.KB_EINVAL
+    assert call(wsb=32) == lib.KB_ENOMEM
+    tt = np.arange(65, dtype=np.float64)
+    st = L.kb_stamps(fake, fake, None, 65, 8, 8, tt.ctypes.data, v.ctypes.data, 4, fake, None, 5,
+                     2, 1.0, 1.0, 0.5, 4.0, None, None, fake, fake, 1 << 20, None)
+    assert st == lib.KB_EUNSUPPORTED
