@@ -28,9 +28,12 @@ kb_status upload_tau_vel(const double *t, int64_t n_img, const double *vel, int6
 // Send the gather table (planes of `pix_bytes` bytes per pair; velocities in
 // visiting order unless visiting_order is false) and the visiting order to
 // the workspace (workspace_layout offsets).
+// If dy_range is given it receives the smallest and largest row displacement
+// of the table's real entries.
 kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                        int64_t h, int64_t w, int64_t pix_bytes, void *workspace,
-                       hipStream_t stream, bool visiting_order = true);
+                       hipStream_t stream, bool visiting_order = true,
+                       int32_t *dy_range = nullptr);
 
 // One displacement on the device: floor(v * tau + 0.5) as a separate IEEE
 // double multiply, add and floor (no contraction), clamped to [-lim, lim],

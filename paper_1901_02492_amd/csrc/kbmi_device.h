@@ -37,6 +37,9 @@
 
 // List lengths compiled for the search: every even length up to KB_MAX_KCAND
 // (each slot costs registers and compare-and-swap work on every insertion).
+#ifndef KBMI_INTERIOR
+#define KBMI_INTERIOR 1         // float32: start rows with every displaced row in frame skip the row check
+#endif
 #ifndef KB_SEARCH_KM_LIST
 #define KB_SEARCH_KM_LIST(X)                                                              \
     X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) \
@@ -59,6 +62,7 @@ struct StackView {
     int32_t *cand_vel;
     int16_t *cand_nobs;
     uint32_t *sync;            // per-XCD generation counters of the persistent search
+    int row_lo, row_hi;        // start rows whose displaced rows are all in the frame
 };
 
 // One stack of a batched search, as the batch kernel reads it from device memory.
@@ -365,8 +369,9 @@ constexpr int search_lds_words() {
 }
 
 // The search of one tile (start row `row`, start columns seg*64 .. seg*64+63).
-// All scalar arguments are wave-uniform.
-template <int KM, int NB, int PB, int FMT, bool PF>
+// All scalar arguments are wave-uniform.  INTERIOR: every displaced row of
+// this start row is inside the frame, so the gathers skip the row check.
+template <int KM, int NB, int PB, int FMT, bool PF, bool INTERIOR = false>
 __device__ __forceinline__ void search_tile(
     uint32_t *lds, const void *__restrict__ planes, const float2 *__restrict__ inv_scale,
     int n_img, int h, int w, const GatherEntry *__restrict__ disp, int disp_stride,
@@ -418,9 +423,10 @@ __device__ __forceinline__ void search_tile(
     auto issue = [&](const i32x4(&e)[NB], LoadT(&v)[NB]) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int yy = row + e[b].y;
-            const bool in_rows = (unsigned)yy < (unsigned)h;
             const uint64_t off = ((uint64_t)(uint32_t)e[b].w << 32) | (uint32_t)e[b].z;
+            // Interior tiles: every real entry's row is in the frame; a padding
+            // entry's column (x0 + w) fails the buffer's range check instead.
+            const bool in_rows = INTERIOR || (unsigned)(row + e[b].y) < (unsigned)h;
             const i32x4 rs = buffer_words(row0 + off, in_rows ? row_bytes : 0u);
             if constexpr (FMT == KB_F32)
                 v[b] = raw_load_b64(rs, (x0 + e[b].x) * (int)kPix, 0, 0);
@@ -658,14 +664,18 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     int w, const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
     int n_vel, int k_cand, TileMap tiles, float *__restrict__ cand_nu,
     float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
-    int16_t *__restrict__ cand_nobs) {
+    int16_t *__restrict__ cand_nobs, int row_lo, int row_hi) {
     __shared__ uint32_t lds[search_lds_words<KM, PB>()];
     int row, seg;
     tiles.map(blockIdx.x, row, seg);
-    search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(lds, planes, inv_scale, n_img, h, w, disp,
-                                                     disp_stride,
-                                 vel_index, n_vel, k_cand, row, seg, cand_nu, cand_alpha,
-                                 cand_vel, cand_nobs);
+    if (KBMI_INTERIOR && FMT == KB_F32 && row >= row_lo && row < row_hi)
+        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, FMT == KB_F32>(
+            lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel, k_cand,
+            row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
+    else
+        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(
+            lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel, k_cand,
+            row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
 }
 
 // The single-stack search in the persistent order (large frames).
@@ -675,7 +685,7 @@ __global__ __launch_bounds__(64, 2) void search_persistent_kernel(
     int w, const GatherEntry *__restrict__ disp, int disp_stride,
     const int32_t *__restrict__ vel_index, int n_vel, int k_cand, PersistMap pm,
     float *__restrict__ cand_nu, float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
-    int16_t *__restrict__ cand_nobs, uint32_t *sync) {
+    int16_t *__restrict__ cand_nobs, uint32_t *sync, int row_lo, int row_hi) {
     __shared__ uint32_t lds[search_lds_words<KM, PB>()];
     uint32_t *xcd_count = sync + (blockIdx.x & 7);
     const uint32_t per_xcd = gridDim.x >> 3;
@@ -683,10 +693,16 @@ __global__ __launch_bounds__(64, 2) void search_persistent_kernel(
                           // not all resident, e.g. beside another launch)
     for (int gen = 0; gen < pm.generations; ++gen) {
         int row, seg;
-        if (pm.map(gen, (int)blockIdx.x, row, seg))
-            search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(
-                lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel,
-                k_cand, row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
+        if (pm.map(gen, (int)blockIdx.x, row, seg)) {
+            if (KBMI_INTERIOR && FMT == KB_F32 && row >= row_lo && row < row_hi)
+                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, FMT == KB_F32>(
+                    lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel,
+                    k_cand, row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
+            else
+                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(
+                    lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel,
+                    k_cand, row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
+        }
         // Generation boundary: wait (a bounded time) until every workgroup of
         // this XCD has finished the generation, so its waves start the next
         // block together.  The wait only shapes timing; no result depends on it.

@@ -166,7 +166,9 @@ void gather_table(const double *t, int64_t n_img, const double *vel, int64_t n_v
     }
     std::vector<int32_t> dense(static_cast<size_t>(n_img) * n_vel * 2);
     displacement_table(t, n_img, vel_visit.data(), n_vel, dense.data(), w, h);
-    // Padding entries (0, h): row + h is outside the frame for every start row.
+    // Padding entries (w, h): row + h is outside the frame for every start row,
+    // and column x0 + w is outside it for every start column, so a padding
+    // entry reads nothing whether a load's buffer covers its row or not.
     const int64_t stride = table_stride(n_img);
     const int64_t row_bytes = w * pix_bytes, image_bytes = h * row_bytes;
     for (int64_t j = 0; j < n_vel; ++j)
@@ -177,7 +179,7 @@ void gather_table(const double *t, int64_t n_img, const double *vel, int64_t n_v
                 e.dy = dense[(j * n_img + i) * 2 + 1];
                 e.offset = i * image_bytes + static_cast<int64_t>(e.dy) * row_bytes;
             } else {
-                e.dx = 0;
+                e.dx = static_cast<int32_t>(w);
                 e.dy = static_cast<int32_t>(h);
                 e.offset = 0;
             }

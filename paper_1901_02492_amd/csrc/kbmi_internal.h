@@ -44,7 +44,8 @@ static_assert(sizeof(GatherEntry) == 16, "gather entries are fetched as 16-byte 
 // Device workspace layout: the gather table at offset 0, one row of
 // table_stride(n_img) entries per velocity in visiting order (a multiple of
 // 16; rows are padded with entries whose row lies outside the frame, so that
-// the search fetches whole batches of 8 or 16 with wide scalar loads), then the
+// the search fetches whole batches of 8 or 16 with wide scalar loads, and
+// whose column is outside the frame too), then the
 // original index of each visited velocity (int32 [n_vel]).
 int64_t table_stride(int64_t n_img);
 size_t table_bytes(int64_t n_img, int64_t n_vel);

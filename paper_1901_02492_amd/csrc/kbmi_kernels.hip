@@ -495,12 +495,24 @@ kb_status upload_tau_vel(const double *t, int64_t n_img, const double *vel, int6
 // visiting order into the workspace, asynchronously on `stream`.
 kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                        int64_t h, int64_t w, int64_t pix_bytes, void *workspace,
-                       hipStream_t stream, bool visiting_order) {
+                       hipStream_t stream, bool visiting_order, int32_t *dy_range) {
     const size_t tb = table_bytes(n_img, n_vel);
     std::vector<char> host(tb + static_cast<size_t>(n_vel) * sizeof(int32_t));
+    const GatherEntry *tab = reinterpret_cast<const GatherEntry *>(host.data());
     gather_table(t, n_img, vel, n_vel, h, w, pix_bytes, visiting_order,
                  reinterpret_cast<GatherEntry *>(host.data()),
                  reinterpret_cast<int32_t *>(host.data() + tb));
+    if (dy_range) {
+        const int64_t stride = table_stride(n_img);
+        int32_t lo = 0, hi = 0;
+        for (int64_t j = 0; j < n_vel; ++j)
+            for (int64_t i = 0; i < n_img; ++i) {
+                lo = std::min(lo, tab[j * stride + i].dy);
+                hi = std::max(hi, tab[j * stride + i].dy);
+            }
+        dy_range[0] = lo;
+        dy_range[1] = hi;
+    }
     // The order follows the (256-byte rounded) table directly in the workspace.
     return staged_copy(workspace, host.data(), host.size(), stream);
 }
@@ -631,7 +643,9 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     if (workspace_bytes < ws_need)
         return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", ws_need, workspace_bytes);
     hipStream_t s = (hipStream_t)stream;
-    st = upload_table(t, n_img, vel, n_vel, h, w, dtype == KB_F32 ? 8 : 4, workspace, s);
+    int32_t dy_range[2] = {0, 0};
+    st = upload_table(t, n_img, vel, n_vel, h, w, dtype == KB_F32 ? 8 : 4, workspace, s, true,
+                      dy_range);
     if (st != KB_OK) return st;
     const int kc = (int)k_cand;
     char *wsb = static_cast<char *>(workspace);
@@ -652,6 +666,10 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     sv.cand_vel = cand_vel;
     sv.cand_nobs = cand_nobs;
     sv.sync = reinterpret_cast<uint32_t *>(wsb + lay.sync);
+    // Start rows whose displaced rows are inside the frame for every image and
+    // velocity: their gathers need no row check.
+    sv.row_lo = (int)std::min<int64_t>(h, -(int64_t)dy_range[0]);
+    sv.row_hi = (int)std::max<int64_t>(0, h - (int64_t)dy_range[1]);
     if (dtype != KB_F32) {
         const int stride = (int)table_stride(n_img);
         hipLaunchKernelGGL(inv_scale_kernel, dim3((stride + 63) / 64), dim3(64), 0, s, lp_scale,

@@ -77,7 +77,7 @@ kb_status launch_one(const StackView &v, hipStream_t s) {
             hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, v.planes, v.inv_scale,
                                v.n_img, v.h, v.w, v.disp, v.disp_stride, v.vel_index, v.n_vel,
                                v.k_cand, pm, v.cand_nu, v.cand_alpha, v.cand_vel, v.cand_nobs,
-                               v.sync);
+                               v.sync, v.row_lo, v.row_hi);
             return launch_status("search_persistent_kernel");
         }
     }
@@ -85,7 +85,7 @@ kb_status launch_one(const StackView &v, hipStream_t s) {
     hipLaunchKernelGGL((search_kernel<KM, NB, PB, KBMI_FMT>), dim3(tm.nblocks), dim3(64), 0, s,
                        v.planes, v.inv_scale, v.n_img, v.h, v.w, v.disp, v.disp_stride,
                        v.vel_index, v.n_vel, v.k_cand, tm, v.cand_nu, v.cand_alpha, v.cand_vel,
-                       v.cand_nobs);
+                       v.cand_nobs, v.row_lo, v.row_hi);
     return launch_status("search_kernel");
 }
 
