@@ -37,6 +37,9 @@
 
 // List lengths compiled for the search: every even length up to KB_MAX_KCAND
 // (each slot costs registers and compare-and-swap work on every insertion).
+#ifndef KBMI_PERSIST_PER_CU
+#define KBMI_PERSIST_PER_CU 8   // persistent grid: at most this many one-wave workgroups per CU
+#endif
 #ifndef KBMI_INTERIOR
 #define KBMI_INTERIOR 1         // float32: start rows with every displaced row in frame skip the row check
 #endif

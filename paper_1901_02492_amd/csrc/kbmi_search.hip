@@ -1,5 +1,7 @@
 // Trajectory-search launchers for one plane format (KBMI_FMT: 0 = float32,
 // 1 = IEEE half, 2 = bfloat16); the build compiles this file once per format.
+#include <algorithm>
+
 #include "kbmi_device.h"
 
 #ifndef KBMI_FMT
@@ -30,20 +32,23 @@ TileMap tile_map(int w, int h) {
     return tm;
 }
 
-// Workgroups of `kernel` the device holds at once (0 if unknown), cached per
-// device and kernel.
-template <typename K>
-int resident_workgroups(K kernel) {
+// Workgroups of the persistent grid for `Kernel` (0 if unknown): the number
+// the device holds at once, at most KBMI_PERSIST_PER_CU per CU, cached per
+// device and per kernel instance.  The cap keeps each XCD's block of start
+// pixels small enough for its L2 when a short candidate list lets more waves
+// fit.
+template <auto Kernel>
+int resident_workgroups() {
     static int cached[64] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, Kernel, 64, 0) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                 hipSuccess)
             return 0;
-        cached[dev] = per_cu * cus;
+        cached[dev] = std::min(per_cu, KBMI_PERSIST_PER_CU) * cus;
     }
     return cached[dev];
 }
@@ -56,7 +61,7 @@ kb_status launch_one(const StackView &v, hipStream_t s) {
     // 16-bit search keeps the super-strip order, which measured faster.
     if (KBMI_PERSIST_BS > 0 && KBMI_FMT == KB_F32) {
         auto kernel = search_persistent_kernel<KM, NB, PB, KBMI_FMT>;
-        const int grid = resident_workgroups(kernel);
+        const int grid = resident_workgroups<search_persistent_kernel<KM, NB, PB, KBMI_FMT>>();
         const int nseg = (v.w + 63) / 64;
         const int per_xcd = grid / 8;
         // Worth it only when the frame holds several generations of blocks.
