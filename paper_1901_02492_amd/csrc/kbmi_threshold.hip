@@ -10,7 +10,8 @@
 // The threshold search gathers and scores exactly as the top-k search does
 // (same table, loads, image order and score functions), so a hit's nu, alpha
 // and n_obs are bitwise the values the top-k path gives that trajectory.  It
-// keeps no list, so it needs few registers and runs many waves per SIMD.
+// keeps no list, so it needs few registers; it runs in the top-k search's
+// paced persistent order with two velocities' gathers in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,14 +28,16 @@ namespace {
 constexpr int TH_NB = 16;          // table entries per batch (the table stride unit)
 constexpr int TH_STRIP = 4;        // tiles per strip of the tile order
 
-// One wave per 64-pixel tile of one start row.
-__global__ __launch_bounds__(64) void search_threshold_kernel(
+#ifndef KBMI_TH_PERSIST
+#define KBMI_TH_PERSIST 1   // threshold search: paced persistent order (float32 search's)
+#endif
+
+// One tile: 64 adjacent start pixels of one row, every velocity.
+__device__ __forceinline__ void threshold_tile(
     const float2 *__restrict__ planes, int n_img, int h, int w,
     const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
-    int n_vel, int nseg, int ntiles, float nu_min, kb_hit *__restrict__ hits, uint64_t cap,
+    int n_vel, int row, int seg, float nu_min, kb_hit *__restrict__ hits, uint64_t cap,
     unsigned long long *__restrict__ n_hits) {
-    int row, seg;
-    strip_tile(xcd_remap((int)blockIdx.x, ntiles), nseg, h, TH_STRIP, row, seg);
     const int lane = (int)threadIdx.x;
     const int x0 = seg * 64 + lane;
     const uint32_t row_bytes = (uint32_t)w * 8u;
@@ -42,40 +45,40 @@ __global__ __launch_bounds__(64) void search_threshold_kernel(
     const const_i32 *visit = (const const_i32 *)(const void *)vel_index;
     const uint64_t below = (uint64_t(1) << lane) - 1;
 
-    for (int jj = 0; jj < n_vel; ++jj) {
-        const int j = visit[jj];
-        float P = 0.f, F = 0.f;
-        uint32_t c = 0;
-        for (int i0 = 0; i0 < n_img; i0 += TH_NB) {
-            const const_i32x4 *t4 =
-                (const const_i32x4 *)(const void *)(disp + (size_t)jj * disp_stride + i0);
-            i32x4 e[TH_NB];
+    auto fetch = [&](int jj, int i0, i32x4(&e)[TH_NB]) {
+        const const_i32x4 *t4 =
+            (const const_i32x4 *)(const void *)(disp + (size_t)jj * disp_stride + i0);
 #pragma unroll
-            for (int b = 0; b < TH_NB; ++b) e[b] = t4[b];
-            u32x2 v[TH_NB];
+        for (int b = 0; b < TH_NB; ++b) e[b] = t4[b];
+    };
+    // Rows outside the frame (padding entries included) get a zero-length
+    // buffer: the load returns 0 without an access.
+    auto issue = [&](const i32x4(&e)[TH_NB], u32x2(&v)[TH_NB]) {
 #pragma unroll
-            for (int b = 0; b < TH_NB; ++b) {
-                // Rows outside the frame (padding entries included) get a
-                // zero-length buffer: the load returns 0 without an access.
-                const int yy = row + e[b].y;
-                const bool in_rows = (unsigned)yy < (unsigned)h;
-                const uint64_t off = ((uint64_t)(uint32_t)e[b].w << 32) | (uint32_t)e[b].z;
-                const i32x4 rs = buffer_words(row0 + off, in_rows ? row_bytes : 0u);
-                v[b] = raw_load_b64(rs, (x0 + e[b].x) * 8, 0, 0);
-            }
-#pragma unroll
-            for (int b = 0; b < TH_NB; ++b) {
-                P += __uint_as_float(v[b].x);
-                F += __uint_as_float(v[b].y);
-                c += min(v[b].y, 1u);
-            }
+        for (int b = 0; b < TH_NB; ++b) {
+            const int yy = row + e[b].y;
+            const bool in_rows = (unsigned)yy < (unsigned)h;
+            const uint64_t off = ((uint64_t)(uint32_t)e[b].w << 32) | (uint32_t)e[b].z;
+            const i32x4 rs = buffer_words(row0 + off, in_rows ? row_bytes : 0u);
+            v[b] = raw_load_b64(rs, (x0 + e[b].x) * 8, 0, 0);
         }
+    };
+    auto accumulate = [&](const u32x2(&v)[TH_NB], float &P, float &F, uint32_t &c) {
+#pragma unroll
+        for (int b = 0; b < TH_NB; ++b) {
+            P += __uint_as_float(v[b].x);
+            F += __uint_as_float(v[b].y);
+            c += min(v[b].y, 1u);
+        }
+    };
+    // Score one trajectory and append it if nu >= nu_min: one atomic per
+    // wave reserves the wave's slots in the list.
+    auto finish = [&](int j, float P, float F, uint32_t c) {
         const float r = inv_sqrt_phi(F);
         const float nu = score_nu(P, F, r);
         const bool pass = x0 < w && nu >= nu_min;
         const uint64_t bal = __ballot(pass);
         if (bal != 0) {
-            // One atomic per wave reserves the wave's slots in the list.
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(n_hits, (unsigned long long)__popcll(bal));
             const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
@@ -93,7 +96,113 @@ __global__ __launch_bounds__(64) void search_threshold_kernel(
                 hits[idx] = hit;
             }
         }
+    };
+
+    if (n_img <= TH_NB) {
+        // Two velocities in flight: the gathers of visit jj+1 are issued
+        // before visit jj is summed and scored; a visit past the end repeats
+        // the last row and is never scored.
+        i32x4 e[TH_NB];
+        u32x2 va[TH_NB], vb[TH_NB];
+        const int last = n_vel - 1;
+        fetch(0, 0, e);
+        issue(e, va);
+        int j_cur = visit[0];
+        int nxt = last < 1 ? last : 1;
+        fetch(nxt, 0, e);
+        int j_nxt = visit[nxt];
+        auto step = [&](int jj, u32x2(&cur)[TH_NB], u32x2(&ahead)[TH_NB]) {
+            issue(e, ahead);
+            __builtin_amdgcn_sched_barrier(0);
+            const int n2 = jj + 2 < last ? jj + 2 : last;
+            fetch(n2, 0, e);
+            const int j2 = visit[n2];
+            __builtin_amdgcn_sched_barrier(0);
+            float P = 0.f, F = 0.f;
+            uint32_t c = 0;
+            accumulate(cur, P, F, c);
+            finish(j_cur, P, F, c);
+            j_cur = j_nxt;
+            j_nxt = j2;
+        };
+        int jj = 0;
+        for (; jj + 1 < n_vel; jj += 2) {
+            step(jj, va, vb);
+            step(jj + 1, vb, va);
+        }
+        if (jj < n_vel) step(jj, va, vb);
+    } else {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            float P = 0.f, F = 0.f;
+            uint32_t c = 0;
+            for (int i0 = 0; i0 < n_img; i0 += TH_NB) {
+                i32x4 e[TH_NB];
+                fetch(jj, i0, e);
+                u32x2 v[TH_NB];
+                issue(e, v);
+                accumulate(v, P, F, c);
+            }
+            finish(visit[jj], P, F, c);
+        }
     }
+}
+
+// Strip tile order, one wave per tile.
+__global__ __launch_bounds__(64) void search_threshold_kernel(
+    const float2 *__restrict__ planes, int n_img, int h, int w,
+    const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
+    int n_vel, int nseg, int ntiles, float nu_min, kb_hit *__restrict__ hits, uint64_t cap,
+    unsigned long long *__restrict__ n_hits) {
+    int row, seg;
+    strip_tile(xcd_remap((int)blockIdx.x, ntiles), nseg, h, TH_STRIP, row, seg);
+    threshold_tile(planes, n_img, h, w, disp, disp_stride, vel_index, n_vel, row, seg, nu_min,
+                   hits, cap, n_hits);
+}
+
+// The paced persistent order of the float32 top-k search: per generation each
+// XCD covers one block of start pixels and its waves wait (a bounded time) for
+// each other at the end of the generation, so that their gathers share the
+// XCD's L2.  The wait only shapes timing.
+__global__ __launch_bounds__(64) void search_threshold_persistent_kernel(
+    const float2 *__restrict__ planes, int n_img, int h, int w,
+    const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
+    int n_vel, PersistMap pm, float nu_min, kb_hit *__restrict__ hits, uint64_t cap,
+    unsigned long long *__restrict__ n_hits, uint32_t *sync) {
+    uint32_t *xcd_count = sync + (blockIdx.x & 7);
+    const uint32_t per_xcd = gridDim.x >> 3;
+    int spin = pm.spin;
+    for (int gen = 0; gen < pm.generations; ++gen) {
+        int row, seg;
+        if (pm.map(gen, (int)blockIdx.x, row, seg))
+            threshold_tile(planes, n_img, h, w, disp, disp_stride, vel_index, n_vel, row, seg,
+                           nu_min, hits, cap, n_hits);
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(xcd_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (uint32_t)(gen + 1) * per_xcd;
+        int i = 0;
+        for (; i < spin; ++i) {
+            if (__hip_atomic_load(xcd_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                target)
+                break;
+            __builtin_amdgcn_s_sleep(8);
+        }
+        if (i == spin) spin = 0;
+    }
+}
+
+int threshold_grid() {
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, search_threshold_persistent_kernel, 64, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = std::min(per_cu, KBMI_PERSIST_PER_CU) * cus;
+    }
+    return cached[dev];
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p) {
@@ -295,6 +404,31 @@ kb_status kb_search_threshold(const float *psi_phi, int64_t n_img, int64_t h, in
     char *ws = static_cast<char *>(workspace);
     const int nseg = (int)((w + 63) / 64);
     const int64_t ntiles = (int64_t)nseg * h;
+    const int grid = KBMI_TH_PERSIST ? threshold_grid() : 0;
+    const int per_xcd = grid / 8;
+    if (grid >= 8 && grid % 8 == 0 && per_xcd % KBMI_PERSIST_BS == 0 && ntiles >= 4 * (int64_t)grid) {
+        PersistMap pm;
+        pm.nseg = nseg;
+        pm.h = (int)h;
+        pm.bs = KBMI_PERSIST_BS;
+        pm.brows = per_xcd / KBMI_PERSIST_BS;
+        pm.nbc = (nseg + pm.bs - 1) / pm.bs;
+        pm.nbr = ((int)h + pm.brows - 1) / pm.brows;
+        pm.generations = (pm.nbc + 7) / 8 * pm.nbr;
+        pm.spin = KBMI_PERSIST_SPIN;
+        uint32_t *sync = reinterpret_cast<uint32_t *>(ws + lay.sync);
+        hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, sync, 8);
+        st = launch_status("zero_words_kernel");
+        if (st != KB_OK) return st;
+        hipLaunchKernelGGL(search_threshold_persistent_kernel, dim3((unsigned)grid), dim3(64), 0,
+                           s, reinterpret_cast<const float2 *>(psi_phi), (int)n_img, (int)h,
+                           (int)w, reinterpret_cast<const GatherEntry *>(ws + lay.table),
+                           (int)table_stride(n_img),
+                           reinterpret_cast<const int32_t *>(ws + lay.order), (int)n_vel, pm,
+                           nu_min, hits, (uint64_t)max_hits,
+                           reinterpret_cast<unsigned long long *>(n_hits), sync);
+        return launch_status("search_threshold_persistent_kernel");
+    }
     hipLaunchKernelGGL(search_threshold_kernel, dim3((unsigned)ntiles), dim3(64), 0, s,
                        reinterpret_cast<const float2 *>(psi_phi), (int)n_img, (int)h, (int)w,
                        reinterpret_cast<const GatherEntry *>(ws + lay.table),
