@@ -40,6 +40,12 @@
 #ifndef KBMI_PERSIST_PER_CU
 #define KBMI_PERSIST_PER_CU 8   // persistent grid: at most this many one-wave workgroups per CU
 #endif
+#ifndef KBMI_NET_MAX_F32
+#define KBMI_NET_MAX_F32 64     // longest list merged by the comparator network (float32)
+#endif
+#ifndef KBMI_NET_MAX_LP
+#define KBMI_NET_MAX_LP 50      // 16-bit planes (their scales take the batch slots' registers)
+#endif
 #ifndef KBMI_INTERIOR
 #define KBMI_INTERIOR 1         // float32: start rows with every displaced row in frame skip the row check
 #endif
@@ -394,7 +400,10 @@ __device__ __forceinline__ void search_tile(
 
     // The list (slots 0..KM-1, descending); with the network merge, slots
     // KM..KM+15 receive the queued batch during a merge.
-    constexpr bool kNet = KM >= 16 && PB == 16;
+    // Longer lists merge one queued entry at a time where the 16 batch slots
+    // would not fit beside the list (16-bit planes also hold their scales).
+    constexpr bool kNet = KM >= 16 && PB == 16 &&
+                          KM <= (FMT == KB_F32 ? KBMI_NET_MAX_F32 : KBMI_NET_MAX_LP);
     constexpr int KR = kNet ? KM + 16 : KM;
     uint64_t key[KR];
     float al[KR];
