@@ -127,6 +127,11 @@ def main():
                     choices=["survey", "small", "serve", "large", "lcfilter", "hits",
                              "threshold", "stamps"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16", "bf16"],
+                    help="survey/hits: plane format searched (16-bit formats are "
+                         "re-scored from the float32 planes by kb_topk)")
+    ap.add_argument("--kcand", type=int, default=None,
+                    help="survey/hits: candidates kept per pixel by the search (default k)")
     ap.add_argument("--requests", type=int, default=None,
                     help="serve: number of requests (default 200); large: per precision (default 6)")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: mean arrivals per second")
@@ -183,8 +188,15 @@ def main():
     img = torch.from_numpy(s.img).to(dev)
     var = torch.from_numpy(s.var).to(dev)
     mask = torch.from_numpy(s.mask).to(dev)
+    lp = None if args.precision == "f32" else args.precision
+    kc = s.k if args.kcand is None else args.kcand
     planes = torch.empty((n, h, w, 2), dtype=torch.float32, device=dev)
-    cand = lib.alloc_candidates(h, w, s.k, dev)
+    lp_planes = lp_scale = None
+    if lp is not None:
+        lp_planes = torch.empty((n, h, w, 2), device=dev,
+                                dtype=torch.float16 if lp == "f16" else torch.bfloat16)
+        lp_scale = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    cand = lib.alloc_candidates(h, w, kc, dev)
     res = lib.alloc_candidates(h, w, s.k, dev)
     ws = lib.alloc_workspace(n, h, w, nv, dev)
     stream = torch.cuda.current_stream()
@@ -194,20 +206,32 @@ def main():
     def step(ev=None):
         if bright is not None:
             lib.mask_bright(img, mask, bright)
-        lib.make_psi_phi(img, var, mask, s.psf, out=planes)
+        if lp is None:
+            lib.make_psi_phi(img, var, mask, s.psf, out=planes)
+        else:
+            lib.make_psi_phi(img, var, mask, s.psf, out=planes, lp=lp, lp_out=lp_planes,
+                             lp_scale=lp_scale)
         if ev is not None:
             ev[0].record(stream)
-        lib.search(planes, s.t, s.vel, s.k, out=cand, workspace=ws)
+        if lp is None:
+            lib.search(planes, s.t, s.vel, kc, out=cand, workspace=ws)
+        else:
+            lib.search(lp_planes, s.t, s.vel, kc, out=cand, workspace=ws, lp_scale=lp_scale)
         if ev is not None:
             ev[1].record(stream)
-        lib.topk(cand, s.k, n, out=res)
+        if lp is None:
+            lib.topk(cand, s.k, n, out=res)
+        else:
+            lib.topk(cand, s.k, n, out=res, rescore=(planes, s.t, s.vel, ws))
+        if ev is not None:
+            ev[2].record(stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log(f"{args.warmup} warmup steps done")
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -216,11 +240,14 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    search_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    log(f"{args.steps} timed steps: {ms_step:.2f} ms/step, search kernel {search_ms:.2f} ms")
+    search_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
+    topk_ms = float(np.mean([b.elapsed_time(c) for _, b, c in evs]))
+    log(f"{args.steps} timed steps: {ms_step:.2f} ms/step, search kernel {search_ms:.2f} ms, "
+        f"{'re-score + ' if lp else ''}top-k {topk_ms:.2f} ms")
 
     tie = s.tie
-    achieved = BYTES_PER_TIE_F32 * tie / (search_ms * 1e-3) / 1e9
+    bytes_per_tie = BYTES_PER_TIE_F32 if lp is None else BYTES_PER_TIE_F32 / 2
+    achieved = bytes_per_tie * tie / (search_ms * 1e-3) / 1e9
     out = {
         "metric": "trajectory-image evals/s",
         "value": tie / (ms_step * 1e-3),
@@ -232,17 +259,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if lp is None else f"{lp} storage, f32 accumulation and re-score",
         "data": "synthetic",
-        "config": {"workload": s.name, "n_img": n, "h": h, "w": w, "n_vel": nv, "k": s.k,
+        "config": {"workload": s.name + ("" if lp is None else f", {lp} planes, K'={kc}"),
+                   "n_img": n, "h": h, "w": w, "n_vel": nv, "k": s.k, "k_cand": kc,
                    "trajectories": h * w * nv, "tie_per_step": tie,
                    "step": ("kb_mask_bright + " if bright is not None else "")
-                           + "kb_make_psi_phi + kb_search + kb_topk",
+                           + "kb_make_psi_phi + kb_search + kb_topk"
+                           + ("" if lp is None else " (re-score from f32 planes)"),
                    "bright_threshold": bright},
         "roofline": {"bound": "hbm", "kernel": "search_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(), "search_ms": search_ms,
-                     "bytes_per_tie": BYTES_PER_TIE_F32},
+                     "traffic": measured_traffic() if (lp is None and kc == s.k
+                                                       and args.workload == "survey") else None,
+                     "search_ms": search_ms, "topk_ms": topk_ms,
+                     "bytes_per_tie": bytes_per_tie},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -271,28 +271,125 @@ __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
 // the float32 search (image order, out-of-frame terms adding +0, the same
 // score expressions), so a re-scored entry is bitwise the plain path's value
 // for that trajectory.  Then every pixel's candidates are ranked by counting.
+//
+// A workgroup owns RS_PX consecutive start pixels and their RS_PX * k_cand
+// (pixel, velocity) pairs.  Gathering the pairs in list order would give each
+// lane of a load its own cache line (the lanes of a wave hold different
+// velocities of one or two pixels).  Instead the pairs are first grouped by
+// velocity with a counting sort in LDS (velocity ranges of n_vel / 1024 when
+// there are more than 1024 velocities), so adjacent lanes mostly share a
+// velocity and read adjacent pixels of one row: a few cache lines per load
+// instead of 64.  The order only changes which lane computes a pair, not its
+// arithmetic.  Results go to LDS by pair, and the ranking reads them in list
+// order.
+// ---------------------------------------------------------------------------
+constexpr int RS_PX = 64;                                   // start pixels per workgroup
+constexpr int RS_BINS = 1024;                               // counting-sort bins
+constexpr int RS_MAXQ = RS_PX * KB_MAX_KCAND / TK_THREADS;  // pairs per thread, at most
+
+size_t rescore_lds_bytes(int k_cand) {
+    const size_t np = (size_t)RS_PX * (size_t)k_cand;
+    return np * 8 + np * 4 + ((np * 2 + 7) & ~(size_t)7) + RS_BINS * 4 + 32;
+}
+
 __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
-    int64_t npix, int h, int w, int n_img, const float2 *__restrict__ planes,
+    int h, int w, int row0, int n_rows, int n_img, const float2 *__restrict__ planes,
     const double *__restrict__ tau, const double2 *__restrict__ vels, int n_vel, int k_cand,
     int k, const int32_t *__restrict__ cand_vel, float *__restrict__ nu,
     float *__restrict__ alpha, int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
-    __shared__ uint64_t s_key[TK_THREADS];
-    const int ppb = TK_THREADS / k_cand;
+    extern __shared__ __align__(16) unsigned char rs_lds[];
+    const int np_max = RS_PX * k_cand;
+    uint64_t *s_key = reinterpret_cast<uint64_t *>(rs_lds);
+    float *s_al = reinterpret_cast<float *>(rs_lds + (size_t)np_max * 8);
+    uint16_t *s_ord = reinterpret_cast<uint16_t *>(rs_lds + (size_t)np_max * 12);
+    uint32_t *s_bin = reinterpret_cast<uint32_t *>(
+        rs_lds + (size_t)np_max * 12 + (((size_t)np_max * 2 + 7) & ~(size_t)7));
+    uint32_t *s_tot = s_bin + RS_BINS;   // 4 wave totals, then the sum
+
+    // Tiles are RS_PX pixels of one row (the last of a row may be shorter).
+    // Workgroups reach the 8 XCDs round-robin, and XCD x walks down tile
+    // columns x, x + 8, ...: at any time the eight XCDs sweep eight adjacent
+    // columns at about the same rows, and the concurrent tiles of one XCD
+    // (about a hundred rows of one column) read overlapping pieces of the
+    // same plane rows through its L2.
+    const int n_ct = (w + RS_PX - 1) / RS_PX;
+    const int64_t kb = (int64_t)(blockIdx.x >> 3);
+    const int64_t ct64 = 8 * (kb / n_rows) + (int64_t)(blockIdx.x & 7u);
+    if (ct64 >= n_ct) return;
+    const int64_t row = row0 + kb % n_rows;
+    const int ct = (int)ct64;
+    const int64_t p0 = row * w + (int64_t)ct * RS_PX;
+    const int npx = min(RS_PX, w - ct * RS_PX);
+    const int np = npx * k_cand;
     const int t = (int)threadIdx.x;
-    const int lp = t / k_cand;
-    const int64_t p = (int64_t)blockIdx.x * ppb + lp;
-    const bool active = lp < ppb && p < npix;
-    uint64_t key = 0;
-    float v_nu = 0.f, v_al = 0.f;
-    int32_t j = 0;
-    uint32_t c = 0;
-    if (active) j = cand_vel[(size_t)p * (size_t)k_cand + (size_t)(t - lp * k_cand)];
-    // A candidate index outside the grid (not written by kb_search) is dropped.
-    const bool scored = active && j >= 0 && j < n_vel;
-    if (scored) {
+    const int nb = n_vel < RS_BINS ? n_vel : RS_BINS;
+    const int32_t *cv = cand_vel + p0 * (int64_t)k_cand;
+
+    for (int b = t; b < RS_BINS; b += TK_THREADS) s_bin[b] = 0u;
+    __syncthreads();
+
+    // Count pairs per bin; remember each pair's bin and place within it.
+    uint32_t slot[RS_MAXQ];
+#pragma unroll
+    for (int r = 0; r < RS_MAXQ; ++r) {
+        const int q = t + r * TK_THREADS;
+        slot[r] = 0xFFFFFFFFu;
+        if (q < np) {
+            const int32_t j = cv[q];
+            // A candidate index outside the grid (not written by kb_search)
+            // is dropped: key 0 ranks below every scored candidate.
+            const bool ok = j >= 0 && j < n_vel;
+            s_key[q] = ok ? (uint64_t)j : 0ull;
+            if (ok) {
+                const uint32_t b = (uint32_t)(((int64_t)j * nb) / n_vel);
+                slot[r] = (b << 16) | atomicAdd(&s_bin[b], 1u);
+            }
+        }
+    }
+    __syncthreads();
+
+    // Exclusive scan of the bin counts: 4 bins per thread, then across lanes
+    // and waves.
+    {
+        uint32_t c4[4], run = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            c4[e] = run;
+            run += s_bin[4 * t + e];
+        }
+        const int lane = t & 63, wv = t >> 6;
+        uint32_t inc = run;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) s_tot[wv] = inc;
+        __syncthreads();
+        uint32_t base = inc - run;
+        for (int v2 = 0; v2 < wv; ++v2) base += s_tot[v2];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s_bin[4 * t + e] = base + c4[e];
+        if (t == TK_THREADS - 1) s_tot[4] = base + run;   // pairs to score
+    }
+    __syncthreads();
+    const int n_sorted = (int)s_tot[4];
+#pragma unroll
+    for (int r = 0; r < RS_MAXQ; ++r)
+        if (slot[r] != 0xFFFFFFFFu)
+            s_ord[s_bin[slot[r] >> 16] + (slot[r] & 0xFFFFu)] = (uint16_t)(t + r * TK_THREADS);
+    __syncthreads();
+
+    // Score the pairs in velocity-grouped order.
+    for (int pos = t; pos < n_sorted; pos += TK_THREADS) {
+        const int q = s_ord[pos];
+        const int j = (int)s_key[q];
+        const int lp = q / k_cand;
+        const int64_t p = p0 + lp;
         const int y0 = (int)(p / w), x0 = (int)(p - (int64_t)y0 * w);
         const double2 vj = vels[j];
         float P = 0.f, F = 0.f;
+        uint32_t c = 0;
         for (int i0 = 0; i0 < n_img; i0 += 8) {
             float2 v[8];
 #pragma unroll
@@ -313,20 +410,35 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
             }
         }
         const float r = inv_sqrt_phi(F);
-        v_nu = score_nu(P, F, r);
-        v_al = score_alpha(v_nu, F, r);
-        key = make_key(v_nu, j, c);
+        const float v_nu = score_nu(P, F, r);
+        s_key[q] = make_key(v_nu, j, c);
+        s_al[q] = score_alpha(v_nu, F, r);
     }
-    s_key[t] = key;
     __syncthreads();
-    int rank = 0;
-    for (int r = 0; r < k_cand; ++r) rank += s_key[lp * k_cand + r] > key;
-    if (active && rank < k) {
-        const size_t o = (size_t)p * (size_t)k + (size_t)rank;
-        nu[o] = scored ? v_nu : -INFINITY;
-        alpha[o] = v_al;
-        vel[o] = j;
-        nobs[o] = (int16_t)c;
+
+    // Rank every pair among its pixel's candidates: keys above it, then equal
+    // keys (only unscored ones can be equal) earlier in the list.
+#pragma unroll
+    for (int r = 0; r < RS_MAXQ; ++r) {
+        const int q = t + r * TK_THREADS;
+        if (q < np) {
+            const int lp = q / k_cand, s = q - lp * k_cand;
+            const uint64_t key = s_key[q];
+            const uint64_t *pk = s_key + lp * k_cand;
+            int rank = 0;
+            for (int u = 0; u < k_cand; ++u) {
+                const uint64_t o = pk[u];
+                rank += (o > key) | ((o == key) & (u < s));
+            }
+            if (rank < k) {
+                const int64_t o = (p0 + lp) * (int64_t)k + rank;
+                const bool scored = key != 0ull;
+                nu[o] = scored ? key_nu(key) : -INFINITY;
+                alpha[o] = scored ? s_al[q] : 0.f;
+                vel[o] = scored ? key_vel(key) : cv[q];
+                nobs[o] = (int16_t)(scored ? key_nobs(key) : 0);
+            }
+        }
     }
 }
 
@@ -373,16 +485,25 @@ __global__ void inv_scale_kernel(const float *__restrict__ scale, int n_img, int
                            : make_float2(0.f, 0.f);
 }
 
-kb_status launch_topk_rescore(int64_t npix, int h, int w, int n_img, const float2 *planes,
-                              const double *tau, const double2 *vels, int n_vel, int k_cand,
-                              int k, const int32_t *cv, float *nu, float *al, int32_t *vi,
-                              int16_t *no, hipStream_t stream) {
-    const int64_t ppb = TK_THREADS / k_cand;
-    const int64_t blocks = (npix + ppb - 1) / ppb;
-    hipLaunchKernelGGL(topk_rescore_kernel, dim3((unsigned)blocks), dim3(TK_THREADS), 0, stream,
-                       npix, h, w, n_img, planes, tau, vels, n_vel, k_cand, k, cv, nu, al, vi,
-                       no);
-    return launch_status("topk_rescore_kernel");
+kb_status launch_topk_rescore(int h, int w, int n_img, const float2 *planes, const double *tau,
+                              const double2 *vels, int n_vel, int k_cand, int k,
+                              const int32_t *cv, float *nu, float *al, int32_t *vi, int16_t *no,
+                              hipStream_t stream) {
+    // Eight workgroups per row for each group of eight tile columns; rows in
+    // launches of at most 2^31 - 1 workgroups.
+    const int64_t n_ct = ((int64_t)w + RS_PX - 1) / RS_PX;
+    const int64_t per_row = 8 * ((n_ct + 7) / 8);
+    const int64_t max_rows = 2147483647LL / per_row;
+    for (int64_t r0 = 0; r0 < h; r0 += max_rows) {
+        const int n_rows = (int)std::min<int64_t>(max_rows, h - r0);
+        hipLaunchKernelGGL(topk_rescore_kernel, dim3((unsigned)(per_row * n_rows)),
+                           dim3(TK_THREADS), rescore_lds_bytes(k_cand), stream, h, w, (int)r0,
+                           n_rows, n_img, planes, tau, vels, n_vel, k_cand, k, cv, nu, al, vi,
+                           no);
+        const kb_status st = launch_status("topk_rescore_kernel");
+        if (st != KB_OK) return st;
+    }
+    return KB_OK;
 }
 
 kb_status launch_topk(int64_t npix, int k_cand, int k, const float *cn, const float *ca,
@@ -717,7 +838,7 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
         st = upload_tau_vel(t, n_img, vel, n_vel, workspace, s, &vel_off);
         if (st != KB_OK) return st;
         char *ws = static_cast<char *>(workspace);
-        return launch_topk_rescore(npix, (int)h, (int)w, (int)n_img,
+        return launch_topk_rescore((int)h, (int)w, (int)n_img,
                                    reinterpret_cast<const float2 *>(psi_phi_f32),
                                    reinterpret_cast<const double *>(ws),
                                    reinterpret_cast<const double2 *>(ws + vel_off), (int)n_vel,

@@ -372,6 +372,65 @@ def test_lp_planes_encoding(torch_dev, lp):
     assert sc[2, 1] > sc[0, 1] * 1e3
 
 
+RESCORE_CASES = [
+    # (seed, n_img, h, w, n_vel, k_cand, k): ragged tiles, odd list lengths,
+    # more velocities than counting-sort bins, the longest list, one pixel.
+    (81, 7, 37, 101, 50, 33, 20),
+    (82, 3, 5, 13, 1500, 64, 64),
+    (83, 15, 130, 300, 600, 50, 50),
+    (84, 4, 64, 64, 64, 64, 9),
+    (85, 2, 1, 1, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("case", RESCORE_CASES, ids=lambda c: "x".join(map(str, c[1:])))
+def test_rescore_of_plain_candidates_equals_topk(torch_dev, case):
+    """kb_topk with re-scoring, given the candidates of a float32 search,
+    recomputes exactly the values the search wrote (same planes, same
+    arithmetic), so its output equals plain kb_topk's bit for bit.  A
+    candidate index outside the grid ranks last with nu = -inf, alpha = 0,
+    n_obs = 0 and its index kept."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    seed, n, h, w, nv, kc, k = case
+    s = synth.random_stack(seed, n=n, h=h, w=w, n_vel=nv, k=k, psf_size=5, vmax=max(h, w))
+    _say(f"case rescore seed={seed} N={n} HxW={h}x{w} V={nv} k_cand={kc} k={k}")
+    dev = torch.device("cuda:0")
+    img, var, mask = (torch.from_numpy(a).to(dev) for a in (s.img, s.var, s.mask))
+    planes = lib.make_psi_phi(img, var, mask, s.psf)
+    ws = lib.alloc_workspace(n, h, w, nv, dev)
+    cand = lib.search(planes, s.t, s.vel, kc, workspace=ws)
+    plain = lib.topk(cand, k, n)
+    again = lib.topk(cand, k, n, rescore=(planes, s.t, s.vel, ws))
+    full = lib.topk(cand, kc, n, rescore=(planes, s.t, s.vel, ws))
+    torch.cuda.synchronize()
+    for a, b in zip(parity.to_numpy(plain), parity.to_numpy(again)):
+        assert np.ascontiguousarray(a).tobytes() == np.ascontiguousarray(b).tobytes()
+    # Corrupt one candidate index per pixel on a stride of pixels.
+    full = [np.ascontiguousarray(a).reshape(h * w, kc) for a in parity.to_numpy(full)]
+    cv = cand[2].clone().reshape(h * w, kc)
+    pix = np.arange(0, h * w, 3)
+    slot = (pix * 7) % kc
+    bad = np.where(pix % 2 == 0, -1, nv).astype(np.int32)
+    pt, st = torch.from_numpy(pix).to(dev), torch.from_numpy(slot).to(dev)
+    cv[pt, st] = torch.from_numpy(bad).to(dev)
+    cand2 = (cand[0], cand[1], cv.reshape(h, w, kc), cand[3])
+    got = lib.topk(cand2, kc, n, rescore=(planes, s.t, s.vel, ws))
+    torch.cuda.synchronize()
+    got = [np.ascontiguousarray(a).reshape(h * w, kc) for a in parity.to_numpy(got)]
+    cv_host = cand[2].reshape(h * w, kc).cpu().numpy()
+    for q, p in enumerate(pix):
+        lost = cv_host[p, slot[q]]
+        keep = full[2][p] != lost
+        for fg, ff in zip(got, full):
+            assert np.array_equal(fg[p, :kc - 1].view(np.uint8), ff[p, keep].view(np.uint8))
+        assert got[0][p, -1] == -np.inf and got[1][p, -1] == 0.0
+        assert got[2][p, -1] == bad[q] and got[3][p, -1] == 0
+    rest = np.setdiff1d(np.arange(h * w), pix)
+    for fg, ff in zip(got, full):
+        assert np.array_equal(fg[rest].view(np.uint8), ff[rest].view(np.uint8))
+
+
 LP_BAND = {"f16": 1e-2, "bf16": 8e-2}   # nu band for near-ties after 16-bit pre-selection
 
 
