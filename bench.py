@@ -276,7 +276,63 @@ def main():
                      "bytes_per_tie": bytes_per_tie},
         "cpu_baseline": cpu,
     }
+    if lp is not None:
+        out["precision"] = precision_vs_f32(lib, torch, planes, cand, res, s, kc, ws)
     print(json.dumps(out), flush=True)
+
+
+def precision_vs_f32(lib, torch, planes, cand, res, s, kc, ws, row_stride=64, chunk_rows=64):
+    """Precision mode against the plain float32 path on the same device, after
+    the timed steps.  `cand` holds the last step's 16-bit candidates and `res`
+    its re-scored top-k.
+      recall: the fraction of the float32 top-k entries (every start pixel)
+              that the 16-bit search kept and the re-score ranked in its top k;
+      equal:  whether every trajectory both keep has bitwise equal values;
+      errors of the 16-bit scores before the re-score, on every row_stride-th
+              row, in the float32 tolerance units: |d nu| / max(1, |nu|) and
+              |d alpha| / max(|alpha|, 1/sqrt(Phi)) with 1/sqrt(Phi) = alpha / nu."""
+    n, h, w, _ = planes.shape
+    k = s.k
+    ref = lib.topk(lib.search(planes, s.t, s.vel, k, workspace=ws), k, n)
+    full = lib.topk(cand, kc, n, rescore=(planes, s.t, s.vel, ws))   # f32 values of every candidate
+    torch.cuda.synchronize()
+    found = 0
+    equal = True
+    for r0 in range(0, h, chunk_rows):
+        r1 = min(h, r0 + chunk_rows)
+        rv, gv = ref[2][r0:r1].reshape(-1, k), res[2][r0:r1].reshape(-1, k)
+        hit = rv[:, :, None] == gv[:, None, :]                 # [pixels, k ref, k got]
+        found += int(hit.any(-1).sum())
+        for fr, fg in zip(ref, res):
+            a = fr[r0:r1].reshape(-1, k)
+            b = fg[r0:r1].reshape(-1, k)
+            if a.dtype == torch.float32:
+                a, b = a.view(torch.int32), b.view(torch.int32)
+            same = (a[:, :, None] == b[:, None, :])
+            equal &= bool(torch.equal(same & hit, hit))
+    rows = torch.arange(0, h, row_stride, device=planes.device)
+    c_nu, c_al, c_v = (t[rows].reshape(-1, kc) for t in cand[:3])
+    f_nu, f_al, f_v = (t[rows].reshape(-1, kc) for t in full[:3])
+    match = c_v[:, :, None] == f_v[:, None, :]                 # [pixels, kc 16-bit, kc f32]
+    idx = match.int().argmax(-1)
+    nu32 = torch.gather(f_nu, 1, idx).double()
+    al32 = torch.gather(f_al, 1, idx).double()
+    ok = match.any(-1) & torch.isfinite(nu32)
+    d_nu = ((c_nu.double() - nu32).abs() / nu32.abs().clamp(min=1.0))[ok]
+    noise = (al32 / nu32).abs()
+    ok_a = ok & (nu32 != 0)
+    d_al = ((c_al.double() - al32).abs() / torch.maximum(al32.abs(), noise))[ok_a]
+
+    def stats(d):
+        d = d.float().cpu().numpy()
+        return {"max": float(d.max()), "p99": float(np.quantile(d, 0.99)), "n": int(d.size)}
+
+    return {"against": "plain float32 search + top-k on the same planes",
+            "recall_vs_f32": found / (h * w * k), "pixels": h * w,
+            "kept_values_bitwise_equal_f32": equal,
+            "nu_err_before_rescore": stats(d_nu), "alpha_err_before_rescore": stats(d_al),
+            "err_sample": f"every {row_stride}th row, all {kc} candidates",
+            "err_units": "|d nu|/max(1,|nu|), |d alpha|/max(|alpha|, 1/sqrt(Phi))"}
 
 
 # --- Light-curve filter ---------------------------------------------------------
