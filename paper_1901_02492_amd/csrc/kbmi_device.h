@@ -480,8 +480,16 @@ __device__ __forceinline__ void search_tile(
         uint32_t c = 0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            if constexpr (FMT == KB_F32) c += min(v[b].y, 1u);
-            else c += min(v[b] >> 16, 1u);
+            if constexpr (FMT == KB_F32) {
+                // min(bits, 1) as one vector instruction: the compiler's
+                // compare-and-carry form routes each term through a scalar
+                // mask and needs wait states before its use.
+                uint32_t m;
+                asm("v_min_u32 %0, %1, 1" : "=v"(m) : "v"(v[b].y));
+                c += m;
+            } else {
+                c += min(v[b] >> 16, 1u);
+            }
         }
         return c;
     };
