@@ -197,7 +197,7 @@ def main():
                                 dtype=torch.float16 if lp == "f16" else torch.bfloat16)
         lp_scale = torch.empty((n, 2), dtype=torch.float32, device=dev)
     cand = lib.alloc_candidates(h, w, kc, dev)
-    res = lib.alloc_candidates(h, w, s.k, dev)
+    res = lib.alloc_candidates(h, w, s.k, dev) if (lp is not None or kc != s.k) else None
     ws = lib.alloc_workspace(n, h, w, nv, dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
@@ -219,7 +219,9 @@ def main():
             lib.search(lp_planes, s.t, s.vel, kc, out=cand, workspace=ws, lp_scale=lp_scale)
         if ev is not None:
             ev[1].record(stream)
-        if lp is None:
+        if lp is None and kc == s.k:
+            lib.topk(cand, s.k, n, out=cand)       # the search's lists, ordered in place
+        elif lp is None:
             lib.topk(cand, s.k, n, out=res)
         else:
             lib.topk(cand, s.k, n, out=res, rescore=(planes, s.t, s.vel, ws))
@@ -266,7 +268,8 @@ def main():
                    "trajectories": h * w * nv, "tie_per_step": tie,
                    "step": ("kb_mask_bright + " if bright is not None else "")
                            + "kb_make_psi_phi + kb_search + kb_topk"
-                           + ("" if lp is None else " (re-score from f32 planes)"),
+                           + (" (re-score from f32 planes)" if lp is not None else
+                              " (in place)" if kc == s.k else ""),
                    "bright_threshold": bright},
         "roofline": {"bound": "hbm", "kernel": "search_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

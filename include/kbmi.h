@@ -207,11 +207,16 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale,
  *   t, vel, n_vel, workspace  as for kb_search (used only when re-scoring).
  *   cand_*       device, as written by kb_search (any order within a pixel;
  *                with re-scoring only cand_vel is read).
- *   nu, alpha, vel_idx, nobs  device out, [h][w][k] in rank order; must not
- *                overlap the candidate arrays.
- * Errors: KB_EINVAL for bad sizes or pointers, k > k_cand, or (re-scoring)
- * bad times/velocities or workspace; KB_ENOMEM for a short workspace;
- * KB_EUNSUPPORTED for k_cand > KB_MAX_KCAND.
+ *   nu, alpha, vel_idx, nobs  device out, [h][w][k] in rank order.  Either
+ *                separate from the candidate arrays, or (k == k_cand, no
+ *                re-scoring) the four candidate arrays themselves: each
+ *                pixel's list is then put in rank order in place, and a block
+ *                of lists already in rank order (as kb_search writes them) is
+ *                checked and not rewritten.
+ * Errors: KB_EINVAL for bad sizes or pointers, k > k_cand, outputs that are
+ * some but not all of the candidate arrays, ordering in place with k < k_cand
+ * or with re-scoring, or (re-scoring) bad times/velocities or workspace;
+ * KB_ENOMEM for a short workspace; KB_EUNSUPPORTED for k_cand > KB_MAX_KCAND.
  */
 kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
                   const double *t, const double *vel, int64_t n_vel,

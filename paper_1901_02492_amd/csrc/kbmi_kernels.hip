@@ -222,14 +222,16 @@ __global__ __launch_bounds__(256) void lp_convert_kernel(
 // the same pixel.  When every pixel of the block is in rank order (kb_search
 // leaves them so) the first k of each are copied out; otherwise each
 // candidate's rank is the number of candidates of its pixel that precede it.
+// In place (outputs are the candidate arrays, k == k_cand) an ordered block
+// writes nothing; every load happens before the block's barrier, so an
+// unordered block can rewrite its own entries.
 // ---------------------------------------------------------------------------
 constexpr int TK_THREADS = 256;
 
 __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
-    int64_t npix, int k_cand, int k, const float *__restrict__ cand_nu,
-    const float *__restrict__ cand_alpha, const int32_t *__restrict__ cand_vel,
-    const int16_t *__restrict__ cand_nobs, float *__restrict__ nu, float *__restrict__ alpha,
-    int32_t *__restrict__ vel, int16_t *__restrict__ nobs) {
+    int64_t npix, int k_cand, int k, bool in_place, const float *cand_nu,
+    const float *cand_alpha, const int32_t *cand_vel, const int16_t *cand_nobs, float *nu,
+    float *alpha, int32_t *vel, int16_t *nobs) {
     __shared__ uint64_t s_key[TK_THREADS];
     const int ppb = TK_THREADS / k_cand;
     const int t = (int)threadIdx.x;
@@ -255,6 +257,8 @@ __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
     if (__syncthreads_or(out_of_order)) {
         rank = 0;
         for (int r = 0; r < k_cand; ++r) rank += s_key[lp * k_cand + r] > key;
+    } else if (in_place) {
+        return;
     }
     if (active && rank < k) {
         const size_t o = (size_t)p * (size_t)k + (size_t)rank;
@@ -506,13 +510,13 @@ kb_status launch_topk_rescore(int h, int w, int n_img, const float2 *planes, con
     return KB_OK;
 }
 
-kb_status launch_topk(int64_t npix, int k_cand, int k, const float *cn, const float *ca,
-                      const int32_t *cv, const int16_t *co, float *nu, float *al, int32_t *vi,
-                      int16_t *no, hipStream_t stream) {
+kb_status launch_topk(int64_t npix, int k_cand, int k, bool in_place, const float *cn,
+                      const float *ca, const int32_t *cv, const int16_t *co, float *nu,
+                      float *al, int32_t *vi, int16_t *no, hipStream_t stream) {
     const int64_t ppb = TK_THREADS / k_cand;
     const int64_t blocks = (npix + ppb - 1) / ppb;
     hipLaunchKernelGGL(topk_kernel, dim3((unsigned)blocks), dim3(TK_THREADS), 0, stream, npix,
-                       k_cand, k, cn, ca, cv, co, nu, al, vi, no);
+                       k_cand, k, in_place, cn, ca, cv, co, nu, al, vi, no);
     return launch_status("topk_kernel");
 }
 
@@ -821,6 +825,19 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
         return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
     const int64_t npix = h * w;
     if ((npix + 3) / 4 > 2147483647LL) return fail(KB_EINVAL, "frame too large");
+    const bool in_place = (const void *)nu == (const void *)cand_nu &&
+                          (const void *)alpha == (const void *)cand_alpha &&
+                          (const void *)vel_idx == (const void *)cand_vel &&
+                          (const void *)nobs == (const void *)cand_nobs;
+    const void *outs[4] = {nu, alpha, vel_idx, nobs};
+    const void *cands[4] = {cand_nu, cand_alpha, cand_vel, cand_nobs};
+    for (const void *o : outs)
+        for (const void *c : cands)
+            if (o == c && !in_place)
+                return fail(KB_EINVAL, "outputs must be the candidate arrays (all four) or "
+                                       "separate from them");
+    if (in_place && (k != k_cand || psi_phi_f32 != nullptr))
+        return fail(KB_EINVAL, "ordering in place needs k == k_cand and no re-scoring");
     if (psi_phi_f32 != nullptr) {
         if (n_vel < 1 || n_vel > 65535)
             return fail(KB_EINVAL, "n_vel must be in [1, 65535] (got %lld)", (long long)n_vel);
@@ -845,8 +862,8 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
                                    (int)k_cand, (int)k, cand_vel, nu, alpha, vel_idx, nobs, s);
     }
     (void)workspace_bytes;
-    return launch_topk(npix, (int)k_cand, (int)k, cand_nu, cand_alpha, cand_vel, cand_nobs, nu,
-                       alpha, vel_idx, nobs, (hipStream_t)stream);
+    return launch_topk(npix, (int)k_cand, (int)k, in_place, cand_nu, cand_alpha, cand_vel,
+                       cand_nobs, nu, alpha, vel_idx, nobs, (hipStream_t)stream);
 }
 
 }  // extern "C"

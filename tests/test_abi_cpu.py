@@ -123,9 +123,33 @@ def test_topk_rescore_checks_times():
     fake = 1 << 20
     t = np.array([0.0, 2.0, 1.0])
     v = np.zeros((4, 2))
+    out = 5 << 20
     st = L.kb_topk(fake, 3, 8, 8, t.ctypes.data, v.ctypes.data, 4, fake, fake, fake, fake, 4, 4,
-                   fake, fake, fake, fake, fake, 1 << 20, None)
+                   out, out + 256, out + 512, out + 768, fake, 1 << 20, None)
     assert st == lib.KB_EINVAL and "non-decreasing" in L.kb_last_error().decode()
+
+
+def test_topk_in_place_argument_checks():
+    """kb_topk's outputs are either all four candidate arrays (k == k_cand, no
+    re-scoring) or separate from them; anything else fails before enqueue."""
+    L = lib.load()
+    a, b, c, d = (1 << 20), (2 << 20), (3 << 20), (4 << 20)
+    o = 5 << 20
+    t = np.array([0.0, 1.0, 2.0])
+    v = np.zeros((4, 2))
+    # one output is a candidate array, the others are not
+    st = L.kb_topk(None, 3, 8, 8, None, None, 0, a, b, c, d, 4, 4, a, o, o + 1, o + 2,
+                   None, 0, None)
+    assert st == lib.KB_EINVAL and "candidate arrays" in L.kb_last_error().decode()
+    st = L.kb_topk(None, 3, 8, 8, None, None, 0, a, b, c, d, 4, 4, o, o + 1, o + 2, a,
+                   None, 0, None)
+    assert st == lib.KB_EINVAL
+    # in place with k < k_cand, or with re-scoring
+    st = L.kb_topk(None, 3, 8, 8, None, None, 0, a, b, c, d, 4, 3, a, b, c, d, None, 0, None)
+    assert st == lib.KB_EINVAL and "in place" in L.kb_last_error().decode()
+    st = L.kb_topk(o, 3, 8, 8, t.ctypes.data, v.ctypes.data, 4, a, b, c, d, 4, 4, a, b, c, d,
+                   o, 1 << 20, None)
+    assert st == lib.KB_EINVAL and "in place" in L.kb_last_error().decode()
 
 
 def test_make_psi_phi_rejects_bad_psf():

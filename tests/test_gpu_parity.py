@@ -334,6 +334,44 @@ def test_topk_orders_shuffled_candidates(torch_dev, kc, k):
         assert np.array_equal(got, np.take_along_axis(src, order, -1))
 
 
+@pytest.mark.parametrize("kc", [50, 64, 7, 1])
+def test_topk_in_place(torch_dev, kc):
+    """kb_topk with the candidate arrays as outputs (k == k_cand): kb_search's
+    lists come back unchanged and equal to the out-of-place result, and
+    shuffled lists (exact nu ties, -inf entries) are put in rank order in
+    place, as a host sort by (nu descending, index ascending) orders them."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    dev = torch.device("cuda:0")
+    s = synth.random_stack(90 + kc, n=6, h=41, w=75, n_vel=max(kc, 70), k=kc, psf_size=5,
+                           vmax=75.0)
+    img, var, mask = (torch.from_numpy(a).to(dev) for a in (s.img, s.var, s.mask))
+    planes = lib.make_psi_phi(img, var, mask, s.psf)
+    cand = lib.search(planes, s.t, s.vel, kc)
+    before = [a.clone() for a in cand]
+    copied = lib.topk(cand, kc, 6)
+    lib.topk(cand, kc, 6, out=cand)
+    torch.cuda.synchronize()
+    for a, b, c in zip(parity.to_numpy(cand), parity.to_numpy(before), parity.to_numpy(copied)):
+        assert a.tobytes() == b.tobytes() == c.tobytes()
+    rng = np.random.default_rng(kc)
+    h, w = 37, 53
+    nu = rng.standard_normal((h, w, kc)).astype(np.float32)
+    nu[..., ::3] = np.round(nu[..., ::3])
+    nu[rng.random(nu.shape) < 0.05] = -np.inf
+    nu[:5] = np.sort(nu[:5], axis=-1)[..., ::-1]        # some rows already ordered
+    vel = np.argsort(rng.random((h, w, 4 * kc)), axis=-1)[..., :kc].astype(np.int32)
+    vel[:5] = np.sort(vel[:5], axis=-1)
+    al = rng.standard_normal((h, w, kc)).astype(np.float32)
+    no = rng.integers(0, 30, (h, w, kc)).astype(np.int16)
+    c2 = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (nu, al, vel, no)]
+    lib.topk(c2, kc, 5, out=c2)
+    torch.cuda.synchronize()
+    order = np.lexsort((vel, -nu.astype(np.float64)), axis=-1)
+    for got, src in zip(parity.to_numpy(c2), (nu, al, vel, no)):
+        assert np.array_equal(got, np.take_along_axis(src, order, -1))
+
+
 # --- precision mode: scaled 16-bit planes, FP32 re-score ---------------------
 
 def _bf16_rne(x):
