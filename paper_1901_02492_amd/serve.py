@@ -214,14 +214,21 @@ class Server:
 # Device executor.
 # ---------------------------------------------------------------------------
 
+def in_place(k, k_cand, lp=None) -> bool:
+    """Whether kb_topk orders the candidate lists in place (plain planes and
+    every candidate kept), so a request needs no separate result buffers."""
+    return lp is None and k_cand == k
+
+
 def footprint_bytes(n_img, h, w, n_vel, k, k_cand, lp=None) -> int:
     """Device bytes one request holds while admitted: inputs (img, var, mask),
-    float32 planes (+ the 16-bit copy), candidates, results, workspace."""
+    float32 planes (+ the 16-bit copy), candidates, results (unless ordered in
+    place), workspace."""
     px = h * w
     inputs = n_img * px * 9
     planes = n_img * px * (8 + (4 if lp else 0))
     cand = px * k_cand * 14
-    out = px * k * 14
+    out = 0 if in_place(k, k_cand, lp) else px * k * 14
     ws = (((n_img + 15) // 16) * 16 * n_vel * 8) + 4 * n_vel + 4096
     return inputs + planes + cand + out + ws
 
@@ -260,7 +267,10 @@ class GpuExecutor:
             else:
                 planes, src, sc = lib.make_psi_phi(img, var, mask, req.psf, lp=self.lp)
             cand = lib.alloc_candidates(h, w, kc, self.dev)
-            out = lib.alloc_candidates(h, w, req.k, self.dev)
+            # Plain planes with every candidate kept: kb_topk orders the
+            # lists in place, so the results are the candidate arrays.
+            out = (cand if in_place(req.k, kc, self.lp)
+                   else lib.alloc_candidates(h, w, req.k, self.dev))
             ws = lib.alloc_workspace(n, h, w, len(req.vel), self.dev)
             ev = torch.cuda.Event()
             ev.record(s)

@@ -152,7 +152,12 @@ def test_late_arrivals_are_admitted_while_others_run():
 
 def test_footprint_counts_every_buffer():
     # 15 x 4096^2, 600 velocities, K = 50: inputs 2.26 GB + planes 2.01 GB +
-    # candidates and results 2 x 11.7 GB.
+    # candidates 11.7 GB, ordered in place (no separate results).
     b = footprint_bytes(15, 4096, 4096, 600, 50, 50)
-    assert 27.6e9 < b < 27.8e9
-    assert footprint_bytes(15, 4096, 4096, 600, 50, 50, lp="f16") - b == 15 * 4096 * 4096 * 4
+    assert 15.9e9 < b < 16.1e9
+    # 16-bit planes: their copy, and results apart from the candidates.
+    assert (footprint_bytes(15, 4096, 4096, 600, 50, 50, lp="f16") - b
+            == 15 * 4096 * 4096 * 4 + 4096 * 4096 * 50 * 14)
+    # more candidates than results: results apart from the candidates.
+    assert (footprint_bytes(15, 4096, 4096, 600, 50, 64) - b
+            == 4096 * 4096 * (64 + 50 - 50) * 14)
