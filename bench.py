@@ -242,7 +242,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    search_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
+    search_each = [a.elapsed_time(b) for a, b, _ in evs]
+    search_ms = float(np.mean(search_each))
     topk_ms = float(np.mean([b.elapsed_time(c) for _, b, c in evs]))
     log(f"{args.steps} timed steps: {ms_step:.2f} ms/step, search kernel {search_ms:.2f} ms, "
         f"{'re-score + ' if lp else ''}top-k {topk_ms:.2f} ms")
@@ -275,7 +276,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if (lp is None and kc == s.k
                                                        and args.workload == "survey") else None,
-                     "search_ms": search_ms, "topk_ms": topk_ms,
+                     "search_ms": search_ms, "search_ms_median": float(np.median(search_each)),
+                     "search_ms_min": float(np.min(search_each)), "topk_ms": topk_ms,
                      "bytes_per_tie": bytes_per_tie},
         "cpu_baseline": cpu,
     }
