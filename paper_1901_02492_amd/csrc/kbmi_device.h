@@ -488,9 +488,14 @@ __device__ __forceinline__ void search_tile(
                 asm("v_min_u32 %0, %1, 1" : "=v"(m) : "v"(v[b].y));
                 c += m;
             } else {
-                c += min(v[b] >> 16, 1u);
+                // Both halves at once: min(psi16, 1) | min(phi16, 1) << 16;
+                // at most 16 terms, so the low half never carries.
+                uint32_t m;
+                asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(v[b]), "v"(0x00010001u));
+                c += m;
             }
         }
+        if constexpr (FMT != KB_F32) c >>= 16;
         return c;
     };
     // One pass of the insertion network: slot s keeps the larger key, the
