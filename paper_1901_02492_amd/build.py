@@ -21,6 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libkbmi.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+KM_GROUPS = 8   # list-length groups of the search units (kKmGroups in kbmi_device.h)
 
 DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -42,9 +43,10 @@ def _run(cmd, verbose):
 def build_library(verbose: bool = False, out: str = LIB, defines=(), jobs: int = 0) -> str:
     """Compile every source and link libkbmi.so (next to this file unless `out`
     is given); `defines` are extra -D options.  The search kernels are compiled
-    once per plane format, all objects in parallel.  Returns the library path."""
+    once per plane format and list-length group, all objects in parallel.
+    Returns the library path."""
     dflags = [f"-D{d}" for d in defines]
-    jobs = jobs or min(8, os.cpu_count() or 1)
+    jobs = jobs or min(16, os.cpu_count() or 1)
     with tempfile.TemporaryDirectory(prefix="kbmi_build_") as tmp:
         steps = [(["g++", *HOST_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_host.cpp"), "-o",
                    os.path.join(tmp, "kbmi_host.o")], os.path.join(tmp, "kbmi_host.o")),
@@ -57,10 +59,16 @@ def build_library(verbose: bool = False, out: str = LIB, defines=(), jobs: int =
                   os.path.join(tmp, "kbmi_threshold.o")),
                  ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_stamps.hip"),
                    "-o", os.path.join(tmp, "kbmi_stamps.o")], os.path.join(tmp, "kbmi_stamps.o"))]
+        # The search kernels: one unit per (plane format, list-length group).
+        search = []
         for fmt in (0, 1, 2):
-            obj = os.path.join(tmp, f"kbmi_search_{fmt}.o")
-            steps.append(([HIPCC, *DEVICE_FLAGS, *dflags, f"-DKBMI_FMT={fmt}", "-c",
-                           os.path.join(CSRC, "kbmi_search.hip"), "-o", obj], obj))
+            for grp in range(KM_GROUPS):
+                obj = os.path.join(tmp, f"kbmi_search_{fmt}_{grp}.o")
+                search.append(([HIPCC, *DEVICE_FLAGS, *dflags, f"-DKBMI_FMT={fmt}",
+                                f"-DKBMI_GROUP={grp}", "-c",
+                                os.path.join(CSRC, "kbmi_search.hip"), "-o", obj], obj))
+        # Longest units first, so the pool ends together.
+        steps = search + steps
         with ThreadPoolExecutor(max_workers=jobs) as pool:
             list(pool.map(lambda st: _run(st[0], verbose), steps))
         tmp_lib = out + ".tmp"

@@ -35,6 +35,22 @@ kb_status upload_table(const double *t, int64_t n_img, const double *vel, int64_
                        hipStream_t stream, bool visiting_order = true,
                        int32_t *dy_range = nullptr);
 
+// Argument checks of kb_search (and its allocation-free variant).
+kb_status check_search_args(const void *planes, int32_t dtype, const float *lp_scale,
+                            int64_t n_img, int64_t h, int64_t w, const double *t,
+                            const double *vel, int64_t n_vel, int64_t k_cand,
+                            const void *cand_nu, const void *cand_alpha, const void *cand_vel,
+                            const void *cand_nobs);
+// Enqueue the search on checked arguments whose tables are already in
+// `workspace` (workspace_layout offsets; the inverse scales of 16-bit planes
+// are written here): dy_range is the smallest and largest row displacement of
+// the table's real entries.
+kb_status launch_search_in(const void *planes, int32_t dtype, const float *lp_scale,
+                           int64_t n_img, int64_t h, int64_t w, int64_t n_vel, int64_t k_cand,
+                           float *cand_nu, float *cand_alpha, int32_t *cand_vel,
+                           int16_t *cand_nobs, void *workspace, const int32_t dy_range[2],
+                           hipStream_t s);
+
 // One displacement on the device: floor(v * tau + 0.5) as a separate IEEE
 // double multiply, add and floor (no contraction), clamped to [-lim, lim],
 // which rounds exactly as the host table does.

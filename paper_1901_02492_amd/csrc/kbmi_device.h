@@ -88,17 +88,35 @@ struct BatchJob {
 
 kb_status launch_status(const char *what);
 
-// Search launchers, one translation unit per plane format; km is the (even)
-// compiled list length >= k_cand.
-kb_status launch_search_f32(int km, const StackView &v, hipStream_t s);
-kb_status launch_search_f16(int km, const StackView &v, hipStream_t s);
-kb_status launch_search_bf16(int km, const StackView &v, hipStream_t s);
-kb_status launch_search_batch_f32(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
-                                  int k_cand, hipStream_t s);
-kb_status launch_search_batch_f16(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
-                                  int k_cand, hipStream_t s);
-kb_status launch_search_batch_bf16(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
-                                   int k_cand, hipStream_t s);
+// Search launchers.  km is the (even) compiled list length >= k_cand.  The
+// list lengths are split into kKmGroups groups, km in group (km / 2 - 1) %
+// kKmGroups, and the build compiles kbmi_search.hip once per plane format and
+// group (the translation units compile in parallel); launch_search and
+// launch_search_batch dispatch to them.
+constexpr int kKmGroups = 8;
+constexpr int km_group(int km) { return (km / 2 - 1) % kKmGroups; }
+template <int FMT, int G>
+kb_status launch_search_group(int km, const StackView &v, hipStream_t s);
+template <int FMT, int G>
+kb_status launch_search_batch_group(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
+                                    int k_cand, hipStream_t s);
+#define KBMI_DECLARE_GROUP(F, G)                                                          \
+    template <>                                                                           \
+    kb_status launch_search_group<F, G>(int, const StackView &, hipStream_t);             \
+    template <>                                                                           \
+    kb_status launch_search_batch_group<F, G>(int, const BatchJob *, int, int, int, hipStream_t);
+#define KBMI_DECLARE_FMT(F)                                                                 \
+    KBMI_DECLARE_GROUP(F, 0) KBMI_DECLARE_GROUP(F, 1) KBMI_DECLARE_GROUP(F, 2)             \
+    KBMI_DECLARE_GROUP(F, 3) KBMI_DECLARE_GROUP(F, 4) KBMI_DECLARE_GROUP(F, 5)             \
+    KBMI_DECLARE_GROUP(F, 6) KBMI_DECLARE_GROUP(F, 7)
+KBMI_DECLARE_FMT(0)
+KBMI_DECLARE_FMT(1)
+KBMI_DECLARE_FMT(2)
+#undef KBMI_DECLARE_FMT
+#undef KBMI_DECLARE_GROUP
+kb_status launch_search(int fmt, int km, const StackView &v, hipStream_t s);
+kb_status launch_search_batch(int fmt, int km, const BatchJob *jobs, int n_jobs,
+                              int total_blocks, int k_cand, hipStream_t s);
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));

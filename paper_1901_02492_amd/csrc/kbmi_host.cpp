@@ -57,42 +57,39 @@ kb_status check_times_velocities(const double *t, int64_t n_img, const double *v
     return KB_OK;
 }
 
+// floor(v * tau + 0.5) as a separately rounded product, sum and floor,
+// clamped to [-clamp, clamp] when clamp > 0.
+static int32_t offset_of(double v, double tau, int64_t clamp) {
+    volatile double prod = v * tau;        // rounded product
+    volatile double shifted = prod + 0.5;  // rounded sum
+    int64_t d = static_cast<int64_t>(std::floor(shifted));
+    if (clamp > 0) d = d < -clamp ? -clamp : (d > clamp ? clamp : d);
+    return static_cast<int32_t>(d);
+}
+
 void displacement_table(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
                         int32_t *disp, int64_t clamp_w, int64_t clamp_h) {
     const double t0 = t[0];
     for (int64_t j = 0; j < n_vel; ++j) {
         for (int64_t i = 0; i < n_img; ++i) {
             const double tau = t[i] - t0;
-            for (int a = 0; a < 2; ++a) {
-                volatile double prod = vel[2 * j + a] * tau;   // rounded product
-                volatile double shifted = prod + 0.5;          // rounded sum
-                int64_t d = static_cast<int64_t>(std::floor(shifted));
-                const int64_t c = a == 0 ? clamp_w : clamp_h;
-                if (c > 0) d = d < -c ? -c : (d > c ? c : d);
-                disp[(j * n_img + i) * 2 + a] = static_cast<int32_t>(d);
-            }
+            disp[(j * n_img + i) * 2] = offset_of(vel[2 * j], tau, clamp_w);
+            disp[(j * n_img + i) * 2 + 1] = offset_of(vel[2 * j + 1], tau, clamp_h);
         }
     }
 }
 
-// Index along a Hilbert curve of order 16 (rotate-and-flip construction).
-static uint32_t hilbert_index(uint32_t x, uint32_t y) {
-    uint32_t d = 0;
-    for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
-        const uint32_t rx = (x & s) ? 1u : 0u;
-        const uint32_t ry = (y & s) ? 1u : 0u;
-        d += s * s * ((3u * rx) ^ ry);
-        if (ry == 0) {
-            if (rx == 1) {
-                x = (s - 1) - (x & (s - 1)) + (x & ~(s - 1));
-                y = (s - 1) - (y & (s - 1)) + (y & ~(s - 1));
-            }
-            const uint32_t tmp = x;
-            x = y;
-            y = tmp;
+void dy_extent(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+               int64_t clamp_h, int32_t out[2]) {
+    int32_t lo = 0, hi = 0;
+    for (int64_t j = 0; j < n_vel; ++j)
+        for (int64_t i = 0; i < n_img; ++i) {
+            const int32_t d = offset_of(vel[2 * j + 1], t[i] - t[0], clamp_h);
+            lo = std::min(lo, d);
+            hi = std::max(hi, d);
         }
-    }
-    return d;
+    out[0] = lo;
+    out[1] = hi;
 }
 
 #ifndef KBMI_HILBERT_ORDER
@@ -112,13 +109,8 @@ void velocity_order(const double *vel, int64_t n_vel, int32_t *order) {
         }
     std::vector<std::pair<uint32_t, int32_t>> keyed(static_cast<size_t>(n_vel));
     for (int64_t j = 0; j < n_vel; ++j) {
-        uint32_t q[2];
-        for (int a = 0; a < 2; ++a) {
-            const double span = hi[a] - lo[a];
-            const double u = span > 0 ? (vel[2 * j + a] - lo[a]) / span : 0.0;
-            q[a] = static_cast<uint32_t>(std::min(65535.0, std::max(0.0, u * 65535.0)));
-        }
-        keyed[static_cast<size_t>(j)] = {hilbert_index(q[0], q[1]), static_cast<int32_t>(j)};
+        keyed[static_cast<size_t>(j)] = {hilbert_key(vel[2 * j], vel[2 * j + 1], lo, hi),
+                                         static_cast<int32_t>(j)};
     }
     std::stable_sort(keyed.begin(), keyed.end(),
                      [](const auto &a, const auto &b) { return a.first < b.first; });

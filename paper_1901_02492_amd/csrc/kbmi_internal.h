@@ -31,6 +31,52 @@ void displacement_table(const double *t, int64_t n_img, const double *vel, int64
 // order gives the same result (ranking uses the original index).
 void velocity_order(const double *vel, int64_t n_vel, int32_t *order);
 
+// Smallest and largest row offset floor(vy * tau_i + 0.5) (clamped to
+// [-clamp_h, clamp_h]) over every velocity and image, with image 0's 0 included.
+void dy_extent(const double *t, int64_t n_img, const double *vel, int64_t n_vel,
+               int64_t clamp_h, int32_t out[2]);
+
+#if defined(__HIPCC__)
+#define KBMI_HD __host__ __device__
+#else
+#define KBMI_HD
+#endif
+
+// Key of a velocity in the visiting order: its index along a Hilbert curve of
+// order 16 (rotate-and-flip construction) over the velocities' bounding box
+// [lo, hi], each axis quantised to 16 bits.  Host and device compute it with
+// the same IEEE operations.
+KBMI_HD inline uint32_t hilbert_index(uint32_t x, uint32_t y) {
+    uint32_t d = 0;
+    for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u;
+        const uint32_t ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = (s - 1) - (x & (s - 1)) + (x & ~(s - 1));
+                y = (s - 1) - (y & (s - 1)) + (y & ~(s - 1));
+            }
+            const uint32_t tmp = x;
+            x = y;
+            y = tmp;
+        }
+    }
+    return d;
+}
+KBMI_HD inline uint32_t hilbert_key(double vx, double vy, const double lo[2],
+                                    const double hi[2]) {
+    uint32_t q[2];
+    const double v[2] = {vx, vy};
+    for (int a = 0; a < 2; ++a) {
+        const double span = hi[a] - lo[a];
+        const double u = span > 0 ? (v[a] - lo[a]) / span : 0.0;
+        const double c = u * 65535.0;
+        q[a] = (uint32_t)(c < 0.0 ? 0.0 : (c > 65535.0 ? 65535.0 : c));
+    }
+    return hilbert_index(q[0], q[1]);
+}
+
 // One entry of the search's gather table (16 bytes): the displacement (dx, dy)
 // of one image for one velocity, and the byte offset of the displaced row from
 // the start row in the planes, image * image_bytes + dy * row_bytes, so that

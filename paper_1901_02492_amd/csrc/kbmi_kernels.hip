@@ -522,6 +522,99 @@ kb_status launch_topk(int64_t npix, int k_cand, int k, bool in_place, const floa
 
 }  // namespace
 
+kb_status check_search_args(const void *planes, int32_t dtype, const float *lp_scale,
+                            int64_t n_img, int64_t h, int64_t w, const double *t,
+                            const double *vel, int64_t n_vel, int64_t k_cand,
+                            const void *cand_nu, const void *cand_alpha, const void *cand_vel,
+                            const void *cand_nobs) {
+    if (!planes || !cand_nu || !cand_alpha || !cand_vel || !cand_nobs)
+        return fail(KB_EINVAL, "planes and candidate outputs must be non-null");
+    kb_status st = check_frame(n_img, h, w);
+    if (st != KB_OK) return st;
+    if (n_vel < 1 || n_vel > 65535)
+        return fail(KB_EINVAL, "n_vel must be in [1, 65535] (got %lld)", (long long)n_vel);
+    if (k_cand < 1 || k_cand > n_vel)
+        return fail(KB_EINVAL, "k_cand must be in [1, n_vel] (got %lld)", (long long)k_cand);
+    if (k_cand > KB_MAX_KCAND)
+        return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
+    st = check_times_velocities(t, n_img, vel, n_vel);
+    if (st != KB_OK) return st;
+    if (dtype != KB_F32 && dtype != KB_F16 && dtype != KB_BF16)
+        return fail(KB_EINVAL, "dtype must be KB_F32, KB_F16 or KB_BF16");
+    if (dtype != KB_F32 && !lp_scale) return fail(KB_EINVAL, "16-bit planes need lp_scale");
+    return KB_OK;
+}
+
+kb_status launch_search_in(const void *planes, int32_t dtype, const float *lp_scale,
+                           int64_t n_img, int64_t h, int64_t w, int64_t n_vel, int64_t k_cand,
+                           float *cand_nu, float *cand_alpha, int32_t *cand_vel,
+                           int16_t *cand_nobs, void *workspace, const int32_t dy_range[2],
+                           hipStream_t s) {
+    char *wsb = static_cast<char *>(workspace);
+    const WorkspaceLayout lay = workspace_layout(n_img, h, w, n_vel);
+    StackView sv;
+    sv.planes = planes;
+    sv.inv_scale = reinterpret_cast<const float2 *>(wsb + lay.inv_scale);
+    sv.n_img = (int)n_img;
+    sv.h = (int)h;
+    sv.w = (int)w;
+    sv.disp = reinterpret_cast<const GatherEntry *>(wsb + lay.table);
+    sv.disp_stride = (int)table_stride(n_img);
+    sv.vel_index = reinterpret_cast<const int32_t *>(wsb + lay.order);
+    sv.n_vel = (int)n_vel;
+    sv.k_cand = (int)k_cand;
+    sv.cand_nu = cand_nu;
+    sv.cand_alpha = cand_alpha;
+    sv.cand_vel = cand_vel;
+    sv.cand_nobs = cand_nobs;
+    sv.sync = reinterpret_cast<uint32_t *>(wsb + lay.sync);
+    // Start rows whose displaced rows are inside the frame for every image and
+    // velocity: their gathers need no row check.
+    sv.row_lo = (int)std::min<int64_t>(h, -(int64_t)dy_range[0]);
+    sv.row_hi = (int)std::max<int64_t>(0, h - (int64_t)dy_range[1]);
+    if (dtype != KB_F32) {
+        const int stride = (int)table_stride(n_img);
+        hipLaunchKernelGGL(inv_scale_kernel, dim3((stride + 63) / 64), dim3(64), 0, s, lp_scale,
+                           (int)n_img, stride, const_cast<float2 *>(sv.inv_scale));
+        const kb_status st = launch_status("inv_scale_kernel");
+        if (st != KB_OK) return st;
+    }
+    return launch_search(dtype, ((int)k_cand + 1) & ~1, sv, s);
+}
+
+// Dispatch to the translation unit of (plane format, list-length group).
+kb_status launch_search(int fmt, int km, const StackView &v, hipStream_t s) {
+    switch (fmt * kKmGroups + km_group(km)) {
+#define KB_GROUP(F, G)                                \
+    case F * kKmGroups + G:                           \
+        return launch_search_group<F, G>(km, v, s);
+#define KB_FMT(F)                                                                    \
+    KB_GROUP(F, 0) KB_GROUP(F, 1) KB_GROUP(F, 2) KB_GROUP(F, 3) KB_GROUP(F, 4)       \
+    KB_GROUP(F, 5) KB_GROUP(F, 6) KB_GROUP(F, 7)
+        KB_FMT(0) KB_FMT(1) KB_FMT(2)
+#undef KB_FMT
+#undef KB_GROUP
+    }
+    return fail(KB_EUNSUPPORTED, "no search compiled for format %d, list length %d", fmt, km);
+}
+
+kb_status launch_search_batch(int fmt, int km, const BatchJob *jobs, int n_jobs,
+                              int total_blocks, int k_cand, hipStream_t s) {
+    switch (fmt * kKmGroups + km_group(km)) {
+#define KB_GROUP(F, G)                                                                    \
+    case F * kKmGroups + G:                                                               \
+        return launch_search_batch_group<F, G>(km, jobs, n_jobs, total_blocks, k_cand, s);
+#define KB_FMT(F)                                                                    \
+    KB_GROUP(F, 0) KB_GROUP(F, 1) KB_GROUP(F, 2) KB_GROUP(F, 3) KB_GROUP(F, 4)       \
+    KB_GROUP(F, 5) KB_GROUP(F, 6) KB_GROUP(F, 7)
+        KB_FMT(0) KB_FMT(1) KB_FMT(2)
+#undef KB_FMT
+#undef KB_GROUP
+    }
+    return fail(KB_EUNSUPPORTED, "no batched search compiled for format %d, list length %d",
+                fmt, km);
+}
+
 kb_status check_frame(int64_t n_img, int64_t h, int64_t w) {
     if (n_img < 1 || n_img > 32767)
         return fail(KB_EINVAL, "n_img must be in [1, 32767] (got %lld)", (long long)n_img);
@@ -745,22 +838,9 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
                     int16_t *cand_nobs, void *workspace, size_t workspace_bytes,
                     void *stream) {
     clear_error();
-    if (!planes || !cand_nu || !cand_alpha || !cand_vel || !cand_nobs)
-        return fail(KB_EINVAL, "planes and candidate outputs must be non-null");
-    kb_status st = check_frame(n_img, h, w);
+    kb_status st = check_search_args(planes, dtype, lp_scale, n_img, h, w, t, vel, n_vel,
+                                     k_cand, cand_nu, cand_alpha, cand_vel, cand_nobs);
     if (st != KB_OK) return st;
-    if (n_vel < 1 || n_vel > 65535)
-        return fail(KB_EINVAL, "n_vel must be in [1, 65535] (got %lld)", (long long)n_vel);
-    if (k_cand < 1 || k_cand > n_vel)
-        return fail(KB_EINVAL, "k_cand must be in [1, n_vel] (got %lld)", (long long)k_cand);
-    if (k_cand > KB_MAX_KCAND)
-        return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
-    st = check_times_velocities(t, n_img, vel, n_vel);
-    if (st != KB_OK) return st;
-    if (dtype != KB_F32 && dtype != KB_F16 && dtype != KB_BF16)
-        return fail(KB_EINVAL, "dtype must be KB_F32, KB_F16 or KB_BF16");
-    if (dtype != KB_F32 && !lp_scale)
-        return fail(KB_EINVAL, "16-bit planes need lp_scale");
     if (!workspace) return fail(KB_EINVAL, "workspace must be non-null");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KB_EINVAL, "workspace must be 256-byte aligned");
@@ -772,40 +852,8 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale, in
     st = upload_table(t, n_img, vel, n_vel, h, w, dtype == KB_F32 ? 8 : 4, workspace, s, true,
                       dy_range);
     if (st != KB_OK) return st;
-    const int kc = (int)k_cand;
-    char *wsb = static_cast<char *>(workspace);
-    const WorkspaceLayout lay = workspace_layout(n_img, h, w, n_vel);
-    StackView sv;
-    sv.planes = planes;
-    sv.inv_scale = reinterpret_cast<const float2 *>(wsb + lay.inv_scale);
-    sv.n_img = (int)n_img;
-    sv.h = (int)h;
-    sv.w = (int)w;
-    sv.disp = reinterpret_cast<const GatherEntry *>(wsb + lay.table);
-    sv.disp_stride = (int)table_stride(n_img);
-    sv.vel_index = reinterpret_cast<const int32_t *>(wsb + lay.order);
-    sv.n_vel = (int)n_vel;
-    sv.k_cand = kc;
-    sv.cand_nu = cand_nu;
-    sv.cand_alpha = cand_alpha;
-    sv.cand_vel = cand_vel;
-    sv.cand_nobs = cand_nobs;
-    sv.sync = reinterpret_cast<uint32_t *>(wsb + lay.sync);
-    // Start rows whose displaced rows are inside the frame for every image and
-    // velocity: their gathers need no row check.
-    sv.row_lo = (int)std::min<int64_t>(h, -(int64_t)dy_range[0]);
-    sv.row_hi = (int)std::max<int64_t>(0, h - (int64_t)dy_range[1]);
-    if (dtype != KB_F32) {
-        const int stride = (int)table_stride(n_img);
-        hipLaunchKernelGGL(inv_scale_kernel, dim3((stride + 63) / 64), dim3(64), 0, s, lp_scale,
-                           (int)n_img, stride, const_cast<float2 *>(sv.inv_scale));
-        st = launch_status("inv_scale_kernel");
-        if (st != KB_OK) return st;
-    }
-    const int km = (kc + 1) & ~1;
-    if (dtype == KB_F16) return launch_search_f16(km, sv, s);
-    if (dtype == KB_BF16) return launch_search_bf16(km, sv, s);
-    return launch_search_f32(km, sv, s);
+    return launch_search_in(planes, dtype, lp_scale, n_img, h, w, n_vel, k_cand, cand_nu,
+                            cand_alpha, cand_vel, cand_nobs, workspace, dy_range, s);
 }
 
 kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
@@ -990,11 +1038,8 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
         }
     }
     const int kc = (int)k_cand;
-    const int km = (kc + 1) & ~1;
     const BatchJob *dj = reinterpret_cast<const BatchJob *>(ws);
-    if (dtype == KB_F16) return launch_search_batch_f16(km, dj, (int)n_jobs, (int)total_blocks, kc, s);
-    if (dtype == KB_BF16) return launch_search_batch_bf16(km, dj, (int)n_jobs, (int)total_blocks, kc, s);
-    return launch_search_batch_f32(km, dj, (int)n_jobs, (int)total_blocks, kc, s);
+    return launch_search_batch(dtype, (kc + 1) & ~1, dj, (int)n_jobs, (int)total_blocks, kc, s);
 }
 
 }  // extern "C"

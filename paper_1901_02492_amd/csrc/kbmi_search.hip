@@ -1,5 +1,6 @@
 // Trajectory-search launchers for one plane format (KBMI_FMT: 0 = float32,
-// 1 = IEEE half, 2 = bfloat16); the build compiles this file once per format.
+// 1 = IEEE half, 2 = bfloat16) and one group of list lengths (KBMI_GROUP);
+// the build compiles this file once per (format, group).
 #include <algorithm>
 
 #include "kbmi_device.h"
@@ -7,16 +8,8 @@
 #ifndef KBMI_FMT
 #error "compile with -DKBMI_FMT=0|1|2"
 #endif
-
-#if KBMI_FMT == 0
-#define KBMI_LAUNCH launch_search_f32
-#define KBMI_LAUNCH_BATCH launch_search_batch_f32
-#elif KBMI_FMT == 1
-#define KBMI_LAUNCH launch_search_f16
-#define KBMI_LAUNCH_BATCH launch_search_batch_f16
-#else
-#define KBMI_LAUNCH launch_search_bf16
-#define KBMI_LAUNCH_BATCH launch_search_batch_bf16
+#ifndef KBMI_GROUP
+#error "compile with -DKBMI_GROUP=0..7"
 #endif
 
 namespace kbmi {
@@ -108,25 +101,44 @@ kb_status launch_batch_km(const BatchJob *jobs, int n_jobs, int total_blocks, in
     return launch_status("search_batch_kernel");
 }
 
+// List lengths of this translation unit's group are compiled; the others are
+// left to their own units (the dispatcher never sends them here).
+template <int K>
+kb_status launch_in_group(const StackView &v, hipStream_t s) {
+    if constexpr (km_group(K) == KBMI_GROUP) return launch_km<K>(v, s);
+    else return fail(KB_EUNSUPPORTED, "list length %d is not compiled in this group", K);
+}
+
+template <int K>
+kb_status launch_batch_in_group(const BatchJob *jobs, int n_jobs, int total_blocks, int k_cand,
+                                hipStream_t s) {
+    if constexpr (km_group(K) == KBMI_GROUP)
+        return launch_batch_km<K>(jobs, n_jobs, total_blocks, k_cand, s);
+    else return fail(KB_EUNSUPPORTED, "list length %d is not compiled in this group", K);
+}
+
 }  // namespace
 
-kb_status KBMI_LAUNCH(int km, const StackView &v, hipStream_t s) {
+template <>
+kb_status launch_search_group<KBMI_FMT, KBMI_GROUP>(int km, const StackView &v, hipStream_t s) {
     switch (km) {
 #define KB_CASE(K) \
     case K:        \
-        return launch_km<K>(v, s);
+        return launch_in_group<K>(v, s);
         KB_SEARCH_KM_LIST(KB_CASE)
 #undef KB_CASE
     }
     return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
 }
 
-kb_status KBMI_LAUNCH_BATCH(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
-                            int k_cand, hipStream_t s) {
+template <>
+kb_status launch_search_batch_group<KBMI_FMT, KBMI_GROUP>(int km, const BatchJob *jobs,
+                                                           int n_jobs, int total_blocks,
+                                                           int k_cand, hipStream_t s) {
     switch (km) {
 #define KB_CASE(K) \
     case K:        \
-        return launch_batch_km<K>(jobs, n_jobs, total_blocks, k_cand, s);
+        return launch_batch_in_group<K>(jobs, n_jobs, total_blocks, k_cand, s);
         KB_SEARCH_KM_LIST(KB_CASE)
 #undef KB_CASE
     }
