@@ -419,6 +419,38 @@ size_t kb_search_batch_workspace_bytes(const kb_job *jobs, int64_t n_jobs);
 kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int64_t k_cand,
                           void *workspace, size_t workspace_bytes, void *stream);
 
+/* Size of the fixed device array behind kb_search_noalloc (per device). */
+#define KB_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/*
+ * kb_search_noalloc - kb_search for callers that cannot allocate memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, rules and results as kb_search (bit for bit:
+ * the same table, the same kernels), without the workspace: the gather
+ * table, visiting order, 16-bit scales and pacing counters live in a fixed
+ * device array of KB_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends.  The call allocates nothing
+ * (no device, pinned or managed memory); times and velocities reach the
+ * device through kernel arguments, and the table is built there.
+ *   Limit: the stack must fit the array:
+ *     kb_search_workspace_bytes(n_img, h, w, n_vel) + 8 n_img + 20 n_vel
+ *     (+ up to 1 KB of alignment) <= KB_NOALLOC_SCRATCH_BYTES,
+ *   e.g. n_img <= 16 with n_vel <= 31000; beyond that it returns
+ *   KB_EUNSUPPORTED and enqueues nothing.
+ *   Sharing: every call on a device uses that device's one array and leaves
+ *   its contents behind.  Calls on one stream are ordered by the stream;
+ *   calls that overlap on one device (other streams, other host threads,
+ *   kb_search_noalloc beside itself) race on the array and must not be made.
+ *   The first call on a device looks up the array's address (not inside a
+ *   graph capture); later calls only enqueue kernels.
+ * Errors: as kb_search, plus KB_EUNSUPPORTED when the stack exceeds the array.
+ */
+kb_status kb_search_noalloc(const void *planes, int32_t dtype, const float *lp_scale,
+                            int64_t n_img, int64_t h, int64_t w,
+                            const double *t, const double *vel, int64_t n_vel, int64_t k_cand,
+                            float *cand_nu, float *cand_alpha, int32_t *cand_vel,
+                            int16_t *cand_nobs, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

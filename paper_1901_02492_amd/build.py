@@ -58,7 +58,10 @@ def build_library(verbose: bool = False, out: str = LIB, defines=(), jobs: int =
                    "-o", os.path.join(tmp, "kbmi_threshold.o")],
                   os.path.join(tmp, "kbmi_threshold.o")),
                  ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_stamps.hip"),
-                   "-o", os.path.join(tmp, "kbmi_stamps.o")], os.path.join(tmp, "kbmi_stamps.o"))]
+                   "-o", os.path.join(tmp, "kbmi_stamps.o")], os.path.join(tmp, "kbmi_stamps.o")),
+                 ([HIPCC, *DEVICE_FLAGS, *dflags, "-c", os.path.join(CSRC, "kbmi_noalloc.hip"),
+                   "-o", os.path.join(tmp, "kbmi_noalloc.o")],
+                  os.path.join(tmp, "kbmi_noalloc.o"))]
         # The search kernels: one unit per (plane format, list-length group).
         search = []
         for fmt in (0, 1, 2):

@@ -48,6 +48,8 @@ _SIGNATURES = {
                                  ctypes.c_double, ctypes.c_double, _p, _p, _p, _p, _sz, _p]),
     "kb_search_batch_workspace_bytes": (_sz, [_p, _i64]),
     "kb_search_batch": (ctypes.c_int, [_p, _i64, _i32, _i64, _p, _sz, _p]),
+    "kb_search_noalloc": (ctypes.c_int, [_p, _i32, _p, _i64, _i64, _i64, _p, _p, _i64, _i64, _p,
+                                         _p, _p, _p, _p]),
 }
 
 
@@ -222,6 +224,28 @@ def search(planes, t, vel, k_cand, out=None, workspace=None, stream=None, lp_sca
                             _dev(co, torch.int16, "cand_nobs"),
                             _dev(workspace, torch.uint8, "workspace"), workspace.numel(),
                             _stream(stream)))
+    return out
+
+
+def search_noalloc(planes, t, vel, k_cand, out=None, stream=None, lp_scale=None):
+    """kb_search_noalloc: kb_search without a workspace (the library's fixed
+    device array holds the tables); same results as search()."""
+    torch = _torch()
+    n, h, w, two = planes.shape
+    assert two == 2
+    code = {torch.float32: KB_F32, torch.float16: KB_F16, torch.bfloat16: KB_BF16}[planes.dtype]
+    sc_ptr = None if code == KB_F32 else _dev(lp_scale, torch.float32, "lp_scale")
+    t = _host_f64(t)
+    vel = _host_f64(vel, 2)
+    if out is None:
+        out = alloc_candidates(h, w, k_cand, planes.device)
+    cn, ca, cv, co = out
+    _check(load().kb_search_noalloc(_dev(planes, planes.dtype, "planes"), code, sc_ptr, n, h, w,
+                                    t.ctypes.data, vel.ctypes.data, vel.shape[0], k_cand,
+                                    _dev(cn, torch.float32, "cand_nu"),
+                                    _dev(ca, torch.float32, "cand_alpha"),
+                                    _dev(cv, torch.int32, "cand_vel"),
+                                    _dev(co, torch.int16, "cand_nobs"), _stream(stream)))
     return out
 
 
