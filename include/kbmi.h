@@ -322,13 +322,16 @@ size_t kb_cluster_workspace_bytes(int64_t n_hits, int64_t n_vel);
  * nu, ties to the smallest (y, x, vel); the result does not depend on the
  * order of `hits`.
  *   hits    device, kb_hit [n_hits] (e.g. kb_search_threshold's list), at
- *           most 256 * 65535 hits, distinct trajectories; a hit whose vel is
+ *           most 2^30 hits, distinct trajectories; a hit whose vel is
  *           outside [0, n_vel) forms a group of its own.
  *   vel     host, float64 [n_vel][2], the grid the hits index.
  *   rep     device out, int32 [n_hits]: index in `hits` of each hit's group
  *           representative (rep[i] == i for representatives).
  *   workspace  device, 256-byte aligned, >= kb_cluster_workspace_bytes.
- * The pair test is O(n_hits^2) (tiles of 256 x 256 hits).
+ * Pairs are found through a grid of cells slightly wider than eps over
+ * (x, y, s*vx, s*vy), kept in a hash table in the workspace: each hit is
+ * tested against the hits of its own and its 80 neighbouring cells, so the
+ * work grows with the hits and their neighbours within eps, not with n^2.
  * Errors: KB_EINVAL for null pointers, bad sizes or velocities, s or eps not
  * finite and >= 0; KB_ENOMEM for a short workspace; KB_EUNSUPPORTED for more
  * hits than one launch covers.
@@ -402,11 +405,15 @@ typedef struct kb_job {
 size_t kb_search_batch_workspace_bytes(const kb_job *jobs, int64_t n_jobs);
 
 /*
- * kb_search_batch - kb_search for several stacks in one launch (the serving
- * path: small stacks share the GPU instead of each under-filling it).  All
- * jobs share `dtype` and `k_cand`.  Each job's candidates are exactly what
- * kb_search would write for it alone (same arithmetic, same order), whatever
- * else is in the batch.
+ * kb_search_batch - kb_search for several stacks in one persistent launch
+ * per image-count class (at most three: n_img <= 8, <= 16, > 16; the serving
+ * path: small stacks share the GPU instead of each under-filling it).  The
+ * launch's grid is what the GPU holds at once; its work items are the jobs'
+ * start-pixel tiles, packed tile after tile, except that a job of float32
+ * planes large enough for kb_search's paced block order starts at a
+ * generation boundary and keeps that order.  All jobs share `dtype` and
+ * `k_cand`.  Each job's candidates are exactly what kb_search would write
+ * for it alone (same arithmetic, same order), whatever else is in the batch.
  *   jobs       host array of n_jobs (1 <= n_jobs <= 4096) descriptors; read
  *              before return.
  *   workspace  device, >= kb_search_batch_workspace_bytes(jobs, n_jobs),

@@ -35,8 +35,6 @@
 #define KBMI_PERSIST_SPIN 4000  // bound of a wave's wait at a generation boundary
 #endif
 
-// List lengths compiled for the search: every even length up to KB_MAX_KCAND
-// (each slot costs registers and compare-and-swap work on every insertion).
 #ifndef KBMI_PERSIST_PER_CU
 #define KBMI_PERSIST_PER_CU 8   // persistent grid: at most this many one-wave workgroups per CU
 #endif
@@ -44,17 +42,19 @@
 #define KBMI_NET_MAX_F32 64     // longest list merged by the comparator network (float32)
 #endif
 #ifndef KBMI_NET_MAX_LP
-#define KBMI_NET_MAX_LP 50      // 16-bit planes (their scales take the batch slots' registers)
+#define KBMI_NET_MAX_LP 64      // 16-bit planes (past 50 their scales move to LDS)
 #endif
 #ifndef KBMI_INTERIOR
 #define KBMI_INTERIOR 1         // float32: start rows with every displaced row in frame skip the row check
 #endif
-#ifndef KB_SEARCH_KM_LIST
-#define KB_SEARCH_KM_LIST(X)                                                              \
-    X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) \
-    X(32) X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50) X(52) X(54) X(56) X(58)  \
-    X(60) X(62) X(64)
-#endif
+// List lengths compiled for the search (each slot costs registers and
+// compare-and-swap work on every insertion); a search keeps k_cand
+// candidates in the shortest compiled list of at least k_cand slots, which
+// gives the same best k_cand.  Every length in this list must be in
+// kKmList below, in the same order.
+#define KB_SEARCH_KM_LIST(X)                                                                \
+    X(2) X(4) X(6) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(36) X(40) X(44) X(48) X(50) \
+    X(52) X(56) X(60) X(64)
 
 namespace kbmi {
 
@@ -74,7 +74,13 @@ struct StackView {
     int row_lo, row_hi;        // start rows whose displaced rows are all in the frame
 };
 
-// One stack of a batched search, as the batch kernel reads it from device memory.
+// One stack of a batched search, as the batch kernel reads it from device
+// memory.  The launch's work items are its jobs' tiles: job j owns items
+// [item_begin_j, item_begin_{j+1}).  A dense job's items are its tiles in
+// strip order; a block job starts at a generation boundary and its items are
+// the paced persistent order of a single-stack search (generation
+// (item - item_begin) / grid, workgroup (item - item_begin) % grid), slots
+// past its frame's edge included and skipped.
 struct BatchJob {
     const void *planes;
     const float2 *inv_scale;
@@ -83,7 +89,12 @@ struct BatchJob {
     float *cand_nu, *cand_alpha;
     int32_t *cand_vel;
     int16_t *cand_nobs;
-    int n_img, h, w, disp_stride, n_vel, nseg, strip, block_begin;
+    int n_img, h, w, disp_stride, n_vel;
+    int item_begin;
+    int nseg;                  // tiles per row
+    int dense;                 // 1: strip order (strip tiles wide); 0: block order
+    int strip;
+    int bs, brows, nbc, nbr;   // block order (PersistMap's fields)
 };
 
 kb_status launch_status(const char *what);
@@ -94,17 +105,33 @@ kb_status launch_status(const char *what);
 // group (the translation units compile in parallel); launch_search and
 // launch_search_batch dispatch to them.
 constexpr int kKmGroups = 8;
-constexpr int km_group(int km) { return (km / 2 - 1) % kKmGroups; }
+constexpr int kKmList[] = {2, 4, 6, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 50, 52, 56, 60, 64};
+constexpr int kKmCount = (int)(sizeof(kKmList) / sizeof(kKmList[0]));
+static_assert(kKmList[kKmCount - 1] == KB_MAX_KCAND, "the longest list is KB_MAX_KCAND");
+constexpr int km_index(int km) {
+    for (int i = 0; i < kKmCount; ++i)
+        if (kKmList[i] == km) return i;
+    return -1;
+}
+constexpr int km_group(int km) { return km_index(km) % kKmGroups; }
+// The compiled list length for k_cand (1 <= k_cand <= KB_MAX_KCAND).
+constexpr int km_for(int k_cand) {
+    for (int i = 0; i < kKmCount; ++i)
+        if (kKmList[i] >= k_cand) return kKmList[i];
+    return -1;
+}
 template <int FMT, int G>
 kb_status launch_search_group(int km, const StackView &v, hipStream_t s);
 template <int FMT, int G>
-kb_status launch_search_batch_group(int km, const BatchJob *jobs, int n_jobs, int total_blocks,
-                                    int k_cand, hipStream_t s);
+kb_status launch_search_batch_group(int km, const BatchJob *jobs, int n_jobs, int n_img_class,
+                                    int k_cand, int generations, uint32_t *sync, int *grid,
+                                    hipStream_t s);
 #define KBMI_DECLARE_GROUP(F, G)                                                          \
     template <>                                                                           \
     kb_status launch_search_group<F, G>(int, const StackView &, hipStream_t);             \
     template <>                                                                           \
-    kb_status launch_search_batch_group<F, G>(int, const BatchJob *, int, int, int, hipStream_t);
+    kb_status launch_search_batch_group<F, G>(int, const BatchJob *, int, int, int, int,    \
+                                              uint32_t *, int *, hipStream_t);
 #define KBMI_DECLARE_FMT(F)                                                                 \
     KBMI_DECLARE_GROUP(F, 0) KBMI_DECLARE_GROUP(F, 1) KBMI_DECLARE_GROUP(F, 2)             \
     KBMI_DECLARE_GROUP(F, 3) KBMI_DECLARE_GROUP(F, 4) KBMI_DECLARE_GROUP(F, 5)             \
@@ -115,8 +142,14 @@ KBMI_DECLARE_FMT(2)
 #undef KBMI_DECLARE_FMT
 #undef KBMI_DECLARE_GROUP
 kb_status launch_search(int fmt, int km, const StackView &v, hipStream_t s);
+// One persistent launch of `generations` generations over the jobs of one
+// image-count class (0: n_img <= 8, 1: <= 16, 2: > 16), whose descriptors
+// (device) already hold their item ranges for a grid of *grid workgroups;
+// sync: 8 per-XCD counters (zeroed here).  With jobs == nullptr nothing is
+// launched and *grid receives that class's grid.
 kb_status launch_search_batch(int fmt, int km, const BatchJob *jobs, int n_jobs,
-                              int total_blocks, int k_cand, hipStream_t s);
+                              int n_img_class, int k_cand, int generations, uint32_t *sync,
+                              int *grid, hipStream_t s);
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
@@ -250,20 +283,29 @@ __device__ __forceinline__ void net_merge(uint64_t (&r)[N], float (&ra)[N]) {
 }
 
 // Scores of one trajectory (Sec. 2.1.5): nu = Psi / sqrt(Phi) and
-// alpha = Psi / Phi, both from the hardware reciprocal square root r of Phi
+// alpha = Psi / Phi; Phi = 0 (no valid observation) gives nu = -inf and
+// alpha = 0.  Every kernel scores with these functions, so equal sums give
+// bitwise equal scores.
+// KBMI_IEEE_SCORE 0: both from the hardware reciprocal square root r of Phi
 // (within 1 ulp for normal inputs; Phi below 2^-100 is scaled by 2^64 first,
-// so no denormal reaches it): nu = Psi * r, alpha = nu * r.  Phi = 0 (no valid
-// observation) gives nu = -inf and alpha = 0.  Every kernel scores with these
-// functions, so equal sums give bitwise equal scores.
+// so no denormal reaches it): nu = Psi * r, alpha = nu * r.
+// KBMI_IEEE_SCORE 1: a correctly rounded square root and divisions.
+#ifndef KBMI_IEEE_SCORE
+#define KBMI_IEEE_SCORE 0
+#endif
 __device__ inline float inv_sqrt_phi(float F) {
+    if (KBMI_IEEE_SCORE) return 0.f;
     const bool tiny = F < 0x1p-100f;
     const float r = __builtin_amdgcn_rsqf(tiny ? F * 0x1p64f : F);
     return tiny ? r * 0x1p32f : r;
 }
 __device__ inline float score_nu(float P, float F, float r) {
+    if (KBMI_IEEE_SCORE) return F > 0.f ? P / sqrtf(F) : -INFINITY;
     return F > 0.f ? P * r : -INFINITY;
 }
-__device__ inline float score_alpha(float nu, float F, float r) {
+__device__ inline float score_alpha(float P, float nu, float F, float r) {
+    if (KBMI_IEEE_SCORE) return F > 0.f ? P / F : 0.f;
+    (void)P;
     return F > 0.f ? nu * r : 0.f;
 }
 
@@ -390,54 +432,50 @@ __device__ inline float lp_value(uint32_t bits16, int fmt) {
 // is bounded to two waves per SIMD: memory-level parallelism comes from the
 // waves, each holding one velocity's NB loads in flight.
 // ---------------------------------------------------------------------------
+// LDS of a search workgroup: the candidate queue (3 words per entry and
+// lane), also used to stage the output (KM words per lane), then the inverse
+// scales of 16-bit planes of up to kSearchScaleWords / 2 images.
+constexpr int kSearchScaleWords = 128;
 template <int KM, int PB>
-constexpr int search_lds_words() {
+constexpr int search_queue_words() {
     return (3 * PB > KM ? 3 * PB : KM) * 64;
 }
+template <int KM, int PB>
+constexpr int search_lds_words() {
+    return search_queue_words<KM, PB>() + kSearchScaleWords;
+}
 
-// The search of one tile (start row `row`, start columns seg*64 .. seg*64+63).
-// All scalar arguments are wave-uniform.  INTERIOR: every displaced row of
-// this start row is inside the frame, so the gathers skip the row check.
-template <int KM, int NB, int PB, int FMT, bool PF, bool INTERIOR = false>
-__device__ __forceinline__ void search_tile(
-    uint32_t *lds, const void *__restrict__ planes, const float2 *__restrict__ inv_scale,
+// The gathers of one tile (start row `row`, start columns seg*64 .. seg*64+63)
+// for every velocity in the host-chosen visiting order: per velocity each lane
+// sums its trajectory's N (psi, phi) pairs in image order (one coalesced
+// 64 * pair-size run per image across the wave) and counts n_obs, then calls
+// finish(j, Psi, Phi, n_obs) with the velocity's original index j.  All
+// scalar arguments are wave-uniform.
+//   NB        loads per batch (8 or 16; the table stride is a multiple of 16)
+//   PF        fetch the next table row while the gathers are in flight
+//   PIPE      two batches' gathers in flight (PF only; costs a second buffer)
+//   MB        more images than one batch (launched for n_img > NB only)
+//   INTERIOR  every displaced row of this start row is inside the frame
+//   LDS_SC    16-bit planes in one batch: the inverse scales are read from LDS
+//             per velocity instead of held in 2 NB vector registers (for
+//             long lists, whose slots need those registers)
+//   sc_lds    16-bit planes with MB or LDS_SC: LDS for kSearchScaleWords
+//             inverse scales
+template <int NB, int FMT, bool PF, bool PIPE, bool MB, bool INTERIOR, bool LDS_SC,
+          class Finish>
+__device__ __forceinline__ void visit_velocities(
+    float *sc_lds, const void *__restrict__ planes, const float2 *__restrict__ inv_scale,
     int n_img, int h, int w, const GatherEntry *__restrict__ disp, int disp_stride,
-    const int32_t *__restrict__ vel_index, int n_vel, int k_cand, int row, int seg,
-    float *__restrict__ cand_nu, float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
-    int16_t *__restrict__ cand_nobs) {
-    uint32_t *q_hi = lds;
-    uint32_t *q_lo = lds + PB * 64;
-    float *q_al = reinterpret_cast<float *>(lds + 2 * PB * 64);
-
+    const int32_t *__restrict__ vel_index, int n_vel, int row, int seg, Finish &&finish) {
     const int lane = (int)threadIdx.x;
     const int x0 = seg * 64 + lane;
     typedef typename PlaneLoad<FMT>::type LoadT;
     constexpr uint32_t kPix = FMT == KB_F32 ? 8u : 4u;   // bytes per (psi, phi) pair
     const uint32_t row_bytes = (uint32_t)w * kPix;
-    const size_t img_bytes = (size_t)h * (size_t)w * kPix;
-
-    // The list (slots 0..KM-1, descending); with the network merge, slots
-    // KM..KM+15 receive the queued batch during a merge.
-    // Longer lists merge one queued entry at a time where the 16 batch slots
-    // would not fit beside the list (16-bit planes also hold their scales).
-    constexpr bool kNet = KM >= 16 && PB == 16 &&
-                          KM <= (FMT == KB_F32 ? KBMI_NET_MAX_F32 : KBMI_NET_MAX_LP);
-    constexpr int KR = kNet ? KM + 16 : KM;
-    uint64_t key[KR];
-    float al[KR];
-#pragma unroll
-    for (int s = 0; s < KR; ++s) {
-        key[s] = 0;
-        al[s] = 0.f;
-    }
-    uint64_t thr = 0;   // admission threshold (list tail at the last merge)
-    int nq = 0;         // queued candidates of this lane
-
     const const_i32 *visit = (const const_i32 *)(const void *)vel_index;
     // Byte address of the start row in image 0; a table entry's offset moves
     // it to the displaced row of its image.
     const uint64_t row0 = reinterpret_cast<uint64_t>(planes) + (uint64_t)row * row_bytes;
-    (void)img_bytes;
     // Fetch entries [i0, i0 + NB) of table row jj (wide scalar loads).
     auto fetch = [&](int jj, int i0, i32x4(&e)[NB]) {
         const const_i32x4 *t4 =
@@ -445,18 +483,29 @@ __device__ __forceinline__ void search_tile(
 #pragma unroll
         for (int b = 0; b < NB; ++b) e[b] = t4[b];
     };
-    // Issue the gathers of one batch of table entries.  A row outside the
-    // frame (padding entries included) gets a zero-length buffer, so its loads
-    // return 0 and add nothing, with no branch.  With a record count of 0 every
-    // lane fails the range check before an address is formed, so the base of
-    // such a buffer (which may point outside the planes) is never dereferenced.
-    auto issue = [&](const i32x4(&e)[NB], LoadT(&v)[NB]) {
+    // Issue the gathers of one batch of table entries, from entry `from` on
+    // (a compile-time 0 or 1).  A row outside the frame (padding entries
+    // included) gets a zero-length buffer, so its loads return 0 and add
+    // nothing, with no branch.  With a record count of 0 every lane fails the
+    // range check before an address is formed, so the base of such a buffer
+    // (which may point outside the planes) is never dereferenced.  no_entry0:
+    // entry 0 (image 0, whose pair is loaded once per tile) gets a zero-length
+    // buffer too, so its load touches no memory.
+    // nl: entries of this batch that hold images (later ones are padding):
+    // their loads are not issued and their registers hold 0.
+    auto issue = [&](const i32x4(&e)[NB], LoadT(&v)[NB], int from, bool no_entry0, int nl) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+            if (b < from) continue;
+            if (b >= nl) {
+                v[b] = LoadT{};
+                continue;
+            }
             const uint64_t off = ((uint64_t)(uint32_t)e[b].w << 32) | (uint32_t)e[b].z;
             // Interior tiles: every real entry's row is in the frame; a padding
             // entry's column (x0 + w) fails the buffer's range check instead.
-            const bool in_rows = INTERIOR || (unsigned)(row + e[b].y) < (unsigned)h;
+            bool in_rows = INTERIOR || (unsigned)(row + e[b].y) < (unsigned)h;
+            if (b == 0) in_rows = in_rows && !no_entry0;
             const i32x4 rs = buffer_words(row0 + off, in_rows ? row_bytes : 0u);
             if constexpr (FMT == KB_F32)
                 v[b] = raw_load_b64(rs, (x0 + e[b].x) * (int)kPix, 0, 0);
@@ -475,17 +524,19 @@ __device__ __forceinline__ void search_tile(
 #pragma unroll
         for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
     };
-    auto accumulate = [&](const Scales &ss, const LoadT(&v)[NB], float &P, float &F) {
+    auto accumulate = [&](const Scales &ss, const LoadT(&v)[NB], float &P, float &F, int from) {
         if constexpr (FMT == KB_F32) {
             (void)ss;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
+                if (b < from) continue;
                 P += __uint_as_float(v[b].x);
                 F += __uint_as_float(v[b].y);
             }
         } else {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
+                if (b < from) continue;
                 const float isp = (b & 1) ? ss[b / 2].z : ss[b / 2].x;
                 const float isf = (b & 1) ? ss[b / 2].w : ss[b / 2].y;
                 P = fmaf(lp_value(v[b] & 0xFFFFu, FMT), isp, P);
@@ -494,10 +545,11 @@ __device__ __forceinline__ void search_tile(
         }
     };
     // n_obs: the stored phi is nonzero exactly at valid pixels; empty slots are 0.
-    auto count = [&](const LoadT(&v)[NB]) {
+    auto count = [&](const LoadT(&v)[NB], int from) {
         uint32_t c = 0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+            if (b < from) continue;
             if constexpr (FMT == KB_F32) {
                 // min(bits, 1) as one vector instruction: the compiler's
                 // compare-and-carry form routes each term through a scalar
@@ -516,6 +568,272 @@ __device__ __forceinline__ void search_tile(
         if constexpr (FMT != KB_F32) c >>= 16;
         return c;
     };
+    // With all images in one batch the scales are loop-invariant: they are
+    // kept in vector registers (the scalar file holds the table row), or in
+    // LDS (LDS_SC).
+    Scales ss0 = {};
+    if constexpr (FMT != KB_F32 && !MB) {
+        if (n_img <= NB) {
+            if constexpr (LDS_SC) {
+                const float *isc = reinterpret_cast<const float *>(inv_scale);
+                for (int q = lane; q < 2 * NB; q += 64) sc_lds[q] = isc[q];
+                __syncthreads();
+            } else {
+                load_scales(0, ss0);
+#pragma unroll
+                for (int q = 0; q < NB / 2; ++q) asm volatile("" : "+v"(ss0[q]));
+            }
+        }
+    }
+    // Inverse scales of batch `part` from LDS.
+    auto lds_scales = [&](int part, Scales &ss) {
+        const f32x4 *s4 = reinterpret_cast<const f32x4 *>(sc_lds + 2 * NB * part);
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) ss[q] = s4[q];
+    };
+    // Image 0 is the start image: its displacement is (0, 0) for every
+    // velocity (tau_0 = 0), so the pipelined paths load its pair once per tile
+    // and start every trajectory's sums from it, 0 + value first, exactly the
+    // additions the per-velocity loads would make.
+    float P0 = 0.f, F0 = 0.f;
+    uint32_t c0 = 0;
+    auto hoist_image0 = [&](float isp0, float isf0) {
+        const i32x4 rs = buffer_words(row0, row_bytes);
+        if constexpr (FMT == KB_F32) {
+            const u32x2 v0 = raw_load_b64(rs, x0 * (int)kPix, 0, 0);
+            P0 = 0.f + __uint_as_float(v0.x);
+            F0 = 0.f + __uint_as_float(v0.y);
+            asm("v_min_u32 %0, %1, 1" : "=v"(c0) : "v"(v0.y));
+        } else {
+            const uint32_t v0 = raw_load_b32(rs, x0 * (int)kPix, 0, 0);
+            P0 = fmaf(lp_value(v0 & 0xFFFFu, FMT), isp0, 0.f);
+            F0 = fmaf(lp_value(v0 >> 16, FMT), isf0, 0.f);
+            c0 = (v0 >> 16) != 0u ? 1u : 0u;
+        }
+    };
+    constexpr bool kPipe = PF && PIPE;
+    // 16-bit planes of more than one batch keep every image's scales in LDS
+    // (read per batch), up to kMaxLdsScaleImages images.
+    constexpr int kMaxLdsScaleImages = kSearchScaleWords / 2;
+    // The whole visit of one batch after another, for more images than the
+    // pipelined paths take (and lists too long for two batches in flight).
+    auto serial_path = [&]() {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = visit[jj];
+            float P = 0.f, F = 0.f;
+            uint32_t c = 0;
+            for (int i0 = 0; i0 < n_img; i0 += NB) {
+                i32x4 e[NB];
+                fetch(jj, i0, e);
+                LoadT v[NB];
+                issue(e, v, 0, false, NB);
+                Scales ss = {};
+                if constexpr (FMT != KB_F32) load_scales(i0, ss);
+                accumulate(ss, v, P, F, 0);
+                c += count(v, 0);
+            }
+            finish(j, P, F, c);
+        }
+    };
+    if constexpr (MB) {
+        // More images than one batch (MB): launched for n_img > NB only.
+        if (kPipe && (FMT == KB_F32 || n_img <= kMaxLdsScaleImages)) {
+            // Each velocity's table row is read as nbat batches of NB entries,
+            // and the batches of all velocities form one sequence with two
+            // batches in flight (the gathers of batch q+1 are issued before
+            // batch q is summed, the entries of q+2 fetched behind them).  A
+            // velocity's sums run over its batches in image order and it is
+            // scored after its last batch.  Batch 0 of each velocity skips
+            // image 0's memory access (hoisted, as above).
+            const int nbat = (n_img + NB - 1) / NB;
+            if constexpr (FMT != KB_F32) {
+                // (1/s_psi, 1/s_phi) of every image (padding 0) into LDS.
+                const float *isc = reinterpret_cast<const float *>(inv_scale);
+                for (int q = lane; q < 2 * nbat * NB; q += 64) sc_lds[q] = isc[q];
+                __syncthreads();
+                hoist_image0(sc_lds[0], sc_lds[1]);
+            } else {
+                hoist_image0(1.f, 1.f);
+            }
+            const int nq = n_vel * nbat;
+            const int lastq = nq - 1;
+            // Positions (velocity, part) of the batch being summed and of the
+            // batch whose entries sit in e; they advance one batch per step (the
+            // latter stops at the last batch, which the end then repeats).
+            int jj_c = 0, p_c = 0;       // (jj_c is kept for symmetry with the fetch side)
+            int jj_f = 0, p_f = 0;
+            auto advance = [&](int &jj_, int &p_) {
+                if (++p_ == nbat) {
+                    p_ = 0;
+                    ++jj_;
+                }
+            };
+            // Image entries of the last batch of a velocity (the rest pad).
+            const int nl_last = n_img - (nbat - 1) * NB;
+            i32x4 e[NB];
+            LoadT va[NB], vb[NB];
+            fetch(jj_f, p_f * NB, e);
+            issue(e, va, 0, true, NB);
+            int jc = visit[0];           // velocity index of the batch being summed
+            int q_f = 1;                 // flat index of the batch whose entries are in e
+            advance(jj_f, p_f);
+            fetch(jj_f, p_f * NB, e);
+            int je = visit[jj_f];
+            float P = P0, F = F0;
+            uint32_t c = c0;
+            auto step = [&](LoadT(&cur)[NB], LoadT(&ahead)[NB]) {
+                // batch q + 1 (repeats the last at the end)
+                issue(e, ahead, 0, p_f == 0, p_f == nbat - 1 ? nl_last : NB);
+                const int ja = je;
+                __builtin_amdgcn_sched_barrier(0);
+                if (q_f < lastq) {
+                    ++q_f;
+                    advance(jj_f, p_f);
+                }
+                fetch(jj_f, p_f * NB, e);
+                je = visit[jj_f];
+                __builtin_amdgcn_sched_barrier(0);
+                Scales ss = {};
+                if constexpr (FMT != KB_F32) lds_scales(p_c, ss);
+                accumulate(ss, cur, P, F, 0);
+                c += count(cur, 0);
+                if (p_c == nbat - 1) {
+                    finish(jc, P, F, c);
+                    P = P0;
+                    F = F0;
+                    c = c0;
+                }
+                advance(jj_c, p_c);
+                jc = ja;
+            };
+            int q = 0;
+            for (; q + 1 < nq; q += 2) {
+                step(va, vb);
+                step(vb, va);
+            }
+            if (q < nq) step(va, vb);
+        } else {
+            serial_path();
+        }
+    } else if (n_img <= NB && kPipe) {
+        // Two velocities in flight: the gathers of visit jj+1 are issued
+        // before visit jj is summed and scored, and the table row of jj+2 is
+        // fetched behind them (into the registers the row of jj+1 just left).
+        // The load buffers alternate, so the loop runs in pairs of visits; a
+        // visit past the end repeats the last row and is never scored.
+        hoist_image0(ss0[0].x, ss0[0].y);
+        i32x4 e[NB];
+        LoadT va[NB], vb[NB];
+        fetch(0, 0, e);
+        issue(e, va, 1, false, NB);
+        const int last = n_vel - 1;
+        int j_cur = visit[0];
+        int nxt = last < 1 ? last : 1;
+        fetch(nxt, 0, e);
+        int j_nxt = visit[nxt];
+        auto step = [&](int jj, LoadT(&cur)[NB], LoadT(&ahead)[NB]) {
+            issue(e, ahead, 1, false, NB);             // visit jj + 1
+            __builtin_amdgcn_sched_barrier(0);
+            const int n2 = jj + 2 < last ? jj + 2 : last;
+            fetch(n2, 0, e);
+            const int j2 = visit[n2];
+            __builtin_amdgcn_sched_barrier(0);
+            float P = P0, F = F0;
+            accumulate(ss0, cur, P, F, 1);
+            finish(j_cur, P, F, c0 + count(cur, 1));
+            j_cur = j_nxt;
+            j_nxt = j2;
+        };
+        int jj = 0;
+        for (; jj + 1 < n_vel; jj += 2) {
+            step(jj, va, vb);
+            step(jj + 1, vb, va);
+        }
+        if (jj < n_vel) step(jj, va, vb);
+    } else if (n_img <= NB && PF) {
+        // The next velocity's table row is fetched while this velocity's
+        // gathers are in flight (image 0 hoisted as above).
+        if constexpr (LDS_SC) hoist_image0(sc_lds[0], sc_lds[1]);
+        else hoist_image0(ss0[0].x, ss0[0].y);
+        i32x4 e[NB];
+        fetch(0, 0, e);
+        int j_next = visit[0];
+        for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = j_next;
+            LoadT v[NB];
+            issue(e, v, 1, false, NB);
+            // Keep the next row's fetch right behind the gathers (the scheduler
+            // would otherwise sink it below the sums).
+            __builtin_amdgcn_sched_barrier(0);
+            const int jn = jj + 1 < n_vel ? jj + 1 : jj;
+            fetch(jn, 0, e);
+            j_next = visit[jn];
+            __builtin_amdgcn_sched_barrier(0);
+            float P = P0, F = F0;
+            if constexpr (LDS_SC) {
+                Scales ss = {};
+                lds_scales(0, ss);
+                accumulate(ss, v, P, F, 1);
+            } else {
+                accumulate(ss0, v, P, F, 1);
+            }
+            finish(j, P, F, c0 + count(v, 1));
+        }
+    } else if (n_img <= NB) {
+        for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = visit[jj];
+            i32x4 e[NB];
+            fetch(jj, 0, e);
+            LoadT v[NB];
+            issue(e, v, 0, false, NB);
+            float P = 0.f, F = 0.f;
+            if constexpr (LDS_SC) {
+                Scales ss = {};
+                lds_scales(0, ss);
+                accumulate(ss, v, P, F, 0);
+            } else {
+                accumulate(ss0, v, P, F, 0);
+            }
+            finish(j, P, F, count(v, 0));
+        }
+    } else {
+        serial_path();
+    }
+}
+
+// The search of one tile (start row `row`, start columns seg*64 .. seg*64+63).
+// All scalar arguments are wave-uniform.  INTERIOR: every displaced row of
+// this start row is inside the frame, so the gathers skip the row check.
+template <int KM, int NB, int PB, int FMT, bool PF, bool MB, bool INTERIOR = false>
+__device__ __forceinline__ void search_tile(
+    uint32_t *lds, const void *__restrict__ planes, const float2 *__restrict__ inv_scale,
+    int n_img, int h, int w, const GatherEntry *__restrict__ disp, int disp_stride,
+    const int32_t *__restrict__ vel_index, int n_vel, int k_cand, int row, int seg,
+    float *__restrict__ cand_nu, float *__restrict__ cand_alpha, int32_t *__restrict__ cand_vel,
+    int16_t *__restrict__ cand_nobs) {
+    uint32_t *q_hi = lds;
+    uint32_t *q_lo = lds + PB * 64;
+    float *q_al = reinterpret_cast<float *>(lds + 2 * PB * 64);
+
+    const int lane = (int)threadIdx.x;
+
+    // The list (slots 0..KM-1, descending); with the network merge, slots
+    // KM..KM+15 receive the queued batch during a merge.
+    // Longer lists merge one queued entry at a time where the 16 batch slots
+    // would not fit beside the list (16-bit planes also hold their scales).
+    constexpr bool kNet = KM >= 16 && PB == 16 &&
+                          KM <= (FMT == KB_F32 ? KBMI_NET_MAX_F32 : KBMI_NET_MAX_LP);
+    constexpr int KR = kNet ? KM + 16 : KM;
+    uint64_t key[KR];
+    float al[KR];
+#pragma unroll
+    for (int s = 0; s < KR; ++s) {
+        key[s] = 0;
+        al[s] = 0.f;
+    }
+    uint64_t thr = 0;   // admission threshold (list tail at the last merge)
+    int nq = 0;         // queued candidates of this lane
+
     // One pass of the insertion network: slot s keeps the larger key, the
     // smaller moves on (keys within a pixel are distinct, so one compare
     // decides where alpha goes).
@@ -564,109 +882,18 @@ __device__ __forceinline__ void search_tile(
         if (nk > thr) {
             q_hi[nq * 64 + lane] = (uint32_t)(nk >> 32);
             q_lo[nq * 64 + lane] = (uint32_t)nk | c;
-            q_al[nq * 64 + lane] = score_alpha(nu, F, r);
+            q_al[nq * 64 + lane] = score_alpha(P, nu, F, r);
             ++nq;
         }
         if (__any(nq == PB)) merge_queue();
     };
 
-    // With all images in one batch the scales are loop-invariant: they are
-    // kept in vector registers (the scalar file holds the table row).
-    Scales ss0 = {};
-    if constexpr (FMT != KB_F32) {
-        if (n_img <= NB) {
-            load_scales(0, ss0);
-#pragma unroll
-            for (int q = 0; q < NB / 2; ++q) asm volatile("" : "+v"(ss0[q]));
-        }
-    }
     // Two velocities' gathers fit beside the list up to KM = 50 (measured:
     // longer lists spill registers with the second load buffer).
-    constexpr bool kPipe = PF && KBMI_PIPELINE && KM <= 50;
-    if (n_img <= NB && kPipe) {
-        // Two velocities in flight: the gathers of visit jj+1 are issued
-        // before visit jj is summed and scored, and the table row of jj+2 is
-        // fetched behind them (into the registers the row of jj+1 just left).
-        // The load buffers alternate, so the loop runs in pairs of visits; a
-        // visit past the end repeats the last row and is never scored.
-        i32x4 e[NB];
-        LoadT va[NB], vb[NB];
-        fetch(0, 0, e);
-        issue(e, va);
-        const int last = n_vel - 1;
-        int j_cur = visit[0];
-        int nxt = last < 1 ? last : 1;
-        fetch(nxt, 0, e);
-        int j_nxt = visit[nxt];
-        auto step = [&](int jj, LoadT(&cur)[NB], LoadT(&ahead)[NB]) {
-            issue(e, ahead);                       // visit jj + 1
-            __builtin_amdgcn_sched_barrier(0);
-            const int n2 = jj + 2 < last ? jj + 2 : last;
-            fetch(n2, 0, e);
-            const int j2 = visit[n2];
-            __builtin_amdgcn_sched_barrier(0);
-            float P = 0.f, F = 0.f;
-            accumulate(ss0, cur, P, F);
-            finish(j_cur, P, F, count(cur));
-            j_cur = j_nxt;
-            j_nxt = j2;
-        };
-        int jj = 0;
-        for (; jj + 1 < n_vel; jj += 2) {
-            step(jj, va, vb);
-            step(jj + 1, vb, va);
-        }
-        if (jj < n_vel) step(jj, va, vb);
-    } else if (n_img <= NB && PF) {
-        // The next velocity's table row is fetched while this velocity's
-        // gathers are in flight.
-        i32x4 e[NB];
-        fetch(0, 0, e);
-        int j_next = visit[0];
-        for (int jj = 0; jj < n_vel; ++jj) {
-            const int j = j_next;
-            LoadT v[NB];
-            issue(e, v);
-            // Keep the next row's fetch right behind the gathers (the scheduler
-            // would otherwise sink it below the sums).
-            __builtin_amdgcn_sched_barrier(0);
-            const int jn = jj + 1 < n_vel ? jj + 1 : jj;
-            fetch(jn, 0, e);
-            j_next = visit[jn];
-            __builtin_amdgcn_sched_barrier(0);
-            float P = 0.f, F = 0.f;
-            accumulate(ss0, v, P, F);
-            finish(j, P, F, count(v));
-        }
-    } else if (n_img <= NB) {
-        for (int jj = 0; jj < n_vel; ++jj) {
-            const int j = visit[jj];
-            i32x4 e[NB];
-            fetch(jj, 0, e);
-            LoadT v[NB];
-            issue(e, v);
-            float P = 0.f, F = 0.f;
-            accumulate(ss0, v, P, F);
-            finish(j, P, F, count(v));
-        }
-    } else {
-        for (int jj = 0; jj < n_vel; ++jj) {
-            const int j = visit[jj];
-            float P = 0.f, F = 0.f;
-            uint32_t c = 0;
-            for (int i0 = 0; i0 < n_img; i0 += NB) {
-                i32x4 e[NB];
-                fetch(jj, i0, e);
-                LoadT v[NB];
-                issue(e, v);
-                Scales ss = {};
-                if constexpr (FMT != KB_F32) load_scales(i0, ss);
-                accumulate(ss, v, P, F);
-                c += count(v);
-            }
-            finish(j, P, F, c);
-        }
-    }
+    visit_velocities<NB, FMT, PF, (KBMI_PIPELINE != 0 && KM <= 50), MB, INTERIOR,
+                     (FMT != KB_F32 && KM > 50)>(
+        reinterpret_cast<float *>(lds + search_queue_words<KM, PB>()), planes, inv_scale, n_img,
+        h, w, disp, disp_stride, vel_index, n_vel, row, seg, finish);
     merge_queue();
 
     // Write the rank-ordered list: stage each field through LDS so that the
@@ -701,7 +928,7 @@ __device__ __forceinline__ void search_tile(
     }
 }
 
-template <int KM, int NB, int PB, int FMT>
+template <int KM, int NB, int PB, int FMT, bool MB>
 __global__ __launch_bounds__(64, 2) void search_kernel(
     const void *__restrict__ planes, const float2 *__restrict__ inv_scale, int n_img, int h,
     int w, const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
@@ -712,17 +939,17 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     int row, seg;
     tiles.map(blockIdx.x, row, seg);
     if (KBMI_INTERIOR && FMT == KB_F32 && row >= row_lo && row < row_hi)
-        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, FMT == KB_F32>(
+        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB, FMT == KB_F32>(
             lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel, k_cand,
             row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
     else
-        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(
+        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB>(
             lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel, k_cand,
             row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
 }
 
 // The single-stack search in the persistent order (large frames).
-template <int KM, int NB, int PB, int FMT>
+template <int KM, int NB, int PB, int FMT, bool MB>
 __global__ __launch_bounds__(64, 2) void search_persistent_kernel(
     const void *__restrict__ planes, const float2 *__restrict__ inv_scale, int n_img, int h,
     int w, const GatherEntry *__restrict__ disp, int disp_stride,
@@ -738,11 +965,11 @@ __global__ __launch_bounds__(64, 2) void search_persistent_kernel(
         int row, seg;
         if (pm.map(gen, (int)blockIdx.x, row, seg)) {
             if (KBMI_INTERIOR && FMT == KB_F32 && row >= row_lo && row < row_hi)
-                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, FMT == KB_F32>(
+                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB, FMT == KB_F32>(
                     lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel,
                     k_cand, row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
             else
-                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0>(
+                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB>(
                     lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel,
                     k_cand, row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
         }
@@ -768,41 +995,66 @@ __global__ void zero_words_kernel(uint32_t *p, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched search: one launch covers the tiles of several stacks (the serving
-// path).  Job j owns workgroups [block_begin_j, block_begin_{j+1}) of the
-// XCD-remapped order; each tile runs exactly the single-stack search, so a
+// Batched search: one persistent launch covers the tiles of several stacks
+// (the serving path).  The grid is the number of workgroups the GPU holds at
+// once; in generation g, workgroup w processes work item g * grid + w (see
+// BatchJob), then waits with the others of its XCD as in the single-stack
+// persistent search.  Each tile runs exactly the single-stack search, so a
 // stack's results do not depend on what it is batched with.
 // ---------------------------------------------------------------------------
-template <int KM, int PB, int FMT>
-__global__ __launch_bounds__(64, 2) void search_batch_kernel(const BatchJob *__restrict__ jobs,
-                                                             int n_jobs, int total_blocks,
-                                                             int k_cand) {
+template <int KM, int NB, int PB, int FMT, bool MB>
+__global__ __launch_bounds__(64, 2) void search_batch_kernel(const BatchJob *__restrict__ jobs_,
+                                                             int n_jobs, int generations,
+                                                             int spin, int k_cand,
+                                                             uint32_t *sync) {
     __shared__ uint32_t lds[search_lds_words<KM, PB>()];
-    const int t = xcd_remap(blockIdx.x, total_blocks);
-    int lo = 0, hi = n_jobs - 1;   // last job with block_begin <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].block_begin <= t) lo = mid;
-        else hi = mid - 1;
+    // The descriptors do not change during the launch: read through the
+    // constant address space, their fields stay in scalar registers.
+    typedef __attribute__((address_space(4))) const BatchJob CJob;
+    const CJob *jobs = (const CJob *)(const void *)jobs_;
+    uint32_t *xcd_count = sync + (blockIdx.x & 7);
+    const int grid = (int)gridDim.x;
+    const uint32_t per_xcd = gridDim.x >> 3;
+    int j = 0;
+    for (int gen = 0; gen < generations; ++gen) {
+        const int item = gen * grid + (int)blockIdx.x;
+        while (j + 1 < n_jobs && item >= jobs[j + 1].item_begin) ++j;
+        const CJob &jb = jobs[j];
+        const int li = item - jb.item_begin;
+        int row = 0, seg = 0;
+        bool ok;
+        if (jb.dense) {
+            ok = li < jb.nseg * jb.h;
+            if (ok) strip_tile(li, jb.nseg, jb.h, jb.strip, row, seg);
+        } else {
+            PersistMap pm;
+            pm.nseg = jb.nseg;
+            pm.h = jb.h;
+            pm.bs = jb.bs;
+            pm.brows = jb.brows;
+            pm.nbc = jb.nbc;
+            pm.nbr = jb.nbr;
+            const int gl = li / grid;
+            ok = gl < ((jb.nbc + 7) / 8) * jb.nbr && pm.map(gl, li - gl * grid, row, seg);
+        }
+        if (ok)
+            search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB>(
+                lds, jb.planes, jb.inv_scale, jb.n_img, jb.h, jb.w, jb.disp, jb.disp_stride,
+                jb.vel_index, jb.n_vel, k_cand, row, seg, jb.cand_nu, jb.cand_alpha,
+                jb.cand_vel, jb.cand_nobs);
+        // Generation boundary (as in the single-stack persistent search).
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(xcd_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (uint32_t)(gen + 1) * per_xcd;
+        int i = 0;
+        for (; i < spin; ++i) {
+            if (__hip_atomic_load(xcd_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                target)
+                break;
+            __builtin_amdgcn_s_sleep(8);
+        }
+        if (i == spin) spin = 0;
     }
-    // The descriptor is the same for the whole wave; reading its fields
-    // through readfirstlane keeps them (and the table and buffer descriptors
-    // derived from them) in scalar registers.
-    const BatchJob &jb = jobs[__builtin_amdgcn_readfirstlane(lo)];
-    auto u32 = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
-    auto uptr = [](auto *p) {
-        const uint64_t v = reinterpret_cast<uint64_t>(p);
-        const uint64_t lo32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-        const uint64_t hi32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-        return reinterpret_cast<decltype(p)>(lo32 | (hi32 << 32));
-    };
-    int row, seg;
-    const int h = u32(jb.h);
-    strip_tile(t - u32(jb.block_begin), u32(jb.nseg), h, u32(jb.strip), row, seg);
-    search_tile<KM, 16, PB, FMT, false>(
-        lds, uptr(jb.planes), uptr(jb.inv_scale), u32(jb.n_img), h, u32(jb.w), uptr(jb.disp),
-        u32(jb.disp_stride), uptr(jb.vel_index), u32(jb.n_vel), k_cand, row, seg,
-        uptr(jb.cand_nu), uptr(jb.cand_alpha), uptr(jb.cand_vel), uptr(jb.cand_nobs));
 }
 
 }  // namespace

@@ -5,8 +5,11 @@
 // are dropped one at a time (largest first), and nu, alpha and n_obs are
 // recomputed from what remains.
 //
-// One thread per candidate.  Its light curve (at most KB_MAX_LC_IMAGES pairs)
-// is gathered once into registers; the filter then runs in IEEE double with
+// One thread per candidate; a workgroup takes the candidates of a tile of
+// start pixels of one row, grouped by velocity before they are gathered (so
+// the lanes of one load mostly share a velocity and read adjacent pixels).
+// A candidate's light curve (at most KB_MAX_LC_IMAGES pairs) is gathered once
+// into registers; the filter then runs in IEEE double with
 // every product, sum and quotient rounded separately, so that each keep or
 // drop decision is a reproducible function of the float32 planes:
 //   prediction over dtau (random-walk flux, variance q per day):
@@ -22,27 +25,33 @@
 // The refit sums the kept pairs in image order in double.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
 #include "kbmi_common.h"
+#include "kbmi_group.h"
 
 namespace kbmi {
 namespace {
 
 constexpr int LC_THREADS = 256;
+constexpr int LC_PAIRS = 4096;                       // pairs of a grouped workgroup, at most
+constexpr int LC_MAXQ = LC_PAIRS / GR_THREADS;       // pairs per thread, at most
+constexpr int LC_PX = 64;                            // start pixels per grouped tile, at most
+static_assert(LC_THREADS == GR_THREADS, "the grouped filter uses the shared grouping");
 
+// The filter of one candidate c (start pixel p, velocity index j; an index
+// outside [0, n_vel) has no observation).
 template <int NB>
-__global__ __launch_bounds__(LC_THREADS) void lightcurve_kernel(
-    int64_t ncand, int k, int h, int w, int n_img, const float2 *__restrict__ planes,
-    const double *__restrict__ tau, const double2 *__restrict__ vels, int n_vel, double c2,
-    double q, const int32_t *__restrict__ cand_vel, float *__restrict__ nu,
-    float *__restrict__ alpha, int16_t *__restrict__ nobs, uint64_t *__restrict__ rejected) {
+__device__ __forceinline__ void filter_candidate(int64_t c, int64_t p, int j, int h, int w, int n_img,
+                                        const float2 *__restrict__ planes,
+                                        const double *__restrict__ tau,
+                                        const double2 *__restrict__ vels, int n_vel, double c2,
+                                        double q, float *__restrict__ nu,
+                                        float *__restrict__ alpha, int16_t *__restrict__ nobs,
+                                        uint64_t *__restrict__ rejected) {
 #pragma clang fp contract(off)
-    const int64_t c = (int64_t)blockIdx.x * LC_THREADS + threadIdx.x;
-    if (c >= ncand) return;
-    const int64_t p = c / k;
-    const int j = cand_vel[c];
     float2 v[NB];
     uint64_t obs = 0;   // bit i: image i observes the trajectory
 #pragma unroll
@@ -145,16 +154,89 @@ __global__ __launch_bounds__(LC_THREADS) void lightcurve_kernel(
     if (rejected) rejected[c] = obs & ~keep;
 }
 
+// One thread per candidate, in list order (lists longer than LC_PAIRS).
+template <int NB>
+__global__ __launch_bounds__(LC_THREADS) void lightcurve_kernel(
+    int64_t ncand, int k, int h, int w, int n_img, const float2 *__restrict__ planes,
+    const double *__restrict__ tau, const double2 *__restrict__ vels, int n_vel, double c2,
+    double q, const int32_t *__restrict__ cand_vel, float *__restrict__ nu,
+    float *__restrict__ alpha, int16_t *__restrict__ nobs, uint64_t *__restrict__ rejected) {
+    const int64_t c = (int64_t)blockIdx.x * LC_THREADS + threadIdx.x;
+    if (c >= ncand) return;
+    filter_candidate<NB>(c, c / k, cand_vel[c], h, w, n_img, planes, tau, vels, n_vel, c2, q,
+                         nu, alpha, nobs, rejected);
+}
+
+// A workgroup per tile of pt start pixels of one row and their pt * k
+// candidates, grouped by velocity before they are gathered (the re-score's
+// grouping); XCD x walks down tile columns x, x + 8, ... as the re-score
+// does, so the eight XCDs sweep adjacent columns at about the same rows.
+template <int NB>
+__global__ __launch_bounds__(LC_THREADS, NB == 16 ? 3 : 1) void lightcurve_grouped_kernel(
+    int k, int pt, int h, int w, int row0, int n_rows, int n_img,
+    const float2 *__restrict__ planes, const double *__restrict__ tau,
+    const double2 *__restrict__ vels, int n_vel, double c2, double q,
+    const int32_t *__restrict__ cand_vel, float *__restrict__ nu, float *__restrict__ alpha,
+    int16_t *__restrict__ nobs, uint64_t *__restrict__ rejected) {
+    __shared__ int32_t s_vj[LC_PAIRS];
+    __shared__ uint16_t s_ord[LC_PAIRS];
+    __shared__ uint32_t s_bin[GR_BINS + 8];
+    const int n_ct = (w + pt - 1) / pt;
+    const int64_t kb = (int64_t)(blockIdx.x >> 3);
+    const int64_t ct64 = 8 * (kb / n_rows) + (int64_t)(blockIdx.x & 7u);
+    if (ct64 >= n_ct) return;
+    const int64_t row = row0 + kb % n_rows;
+    const int ct = (int)ct64;
+    const int64_t p0 = row * w + (int64_t)ct * pt;
+    const int npx = min(pt, w - ct * pt);
+    const int np = npx * k;
+    const int t = (int)threadIdx.x;
+    const int64_t c0 = p0 * (int64_t)k;
+    const int n_sorted = group_pairs_by_velocity<LC_MAXQ>(cand_vel + c0, np, n_vel, s_vj, s_ord,
+                                                          s_bin, s_bin + GR_BINS);
+    for (int pos = t; pos < n_sorted; pos += LC_THREADS) {
+        const int qq = s_ord[pos];
+        filter_candidate<NB>(c0 + qq, p0 + qq / k, s_vj[qq], h, w, n_img, planes, tau, vels,
+                             n_vel, c2, q, nu, alpha, nobs, rejected);
+    }
+    // Candidates whose index is outside the grid have no observation: what
+    // filter_candidate gives them (nu = -inf, alpha = 0, nothing kept).
+    for (int qq = t; qq < np; qq += LC_THREADS)
+        if (s_vj[qq] < 0) {
+            nu[c0 + qq] = -INFINITY;
+            alpha[c0 + qq] = 0.f;
+            nobs[c0 + qq] = 0;
+            if (rejected) rejected[c0 + qq] = 0;
+        }
+}
+
 template <int NB>
 kb_status launch_lightcurve(int64_t ncand, int k, int h, int w, int n_img, const float2 *planes,
                             const double *tau, const double2 *vels, int n_vel, double c2,
                             double q, const int32_t *cv, float *nu, float *al, int16_t *no,
                             uint64_t *rej, hipStream_t s) {
-    const int64_t blocks = (ncand + LC_THREADS - 1) / LC_THREADS;
-    hipLaunchKernelGGL(lightcurve_kernel<NB>, dim3((unsigned)blocks), dim3(LC_THREADS), 0, s,
-                       ncand, k, h, w, n_img, planes, tau, vels, n_vel, c2, q, cv, nu, al, no,
-                       rej);
-    return launch_status("lightcurve_kernel");
+    if (k > LC_PAIRS) {
+        const int64_t blocks = (ncand + LC_THREADS - 1) / LC_THREADS;
+        hipLaunchKernelGGL(lightcurve_kernel<NB>, dim3((unsigned)blocks), dim3(LC_THREADS), 0, s,
+                           ncand, k, h, w, n_img, planes, tau, vels, n_vel, c2, q, cv, nu, al,
+                           no, rej);
+        return launch_status("lightcurve_kernel");
+    }
+    // Eight workgroups per row for each group of eight tile columns; rows in
+    // launches of at most 2^31 - 1 workgroups.
+    const int pt = std::min(LC_PX, LC_PAIRS / k);
+    const int64_t n_ct = ((int64_t)w + pt - 1) / pt;
+    const int64_t per_row = 8 * ((n_ct + 7) / 8);
+    const int64_t max_rows = 2147483647LL / per_row;
+    for (int64_t r0 = 0; r0 < h; r0 += max_rows) {
+        const int n_rows = (int)std::min<int64_t>(max_rows, h - r0);
+        hipLaunchKernelGGL(lightcurve_grouped_kernel<NB>, dim3((unsigned)(per_row * n_rows)),
+                           dim3(LC_THREADS), 0, s, k, pt, h, w, (int)r0, n_rows, n_img, planes,
+                           tau, vels, n_vel, c2, q, cv, nu, al, no, rej);
+        const kb_status st = launch_status("lightcurve_grouped_kernel");
+        if (st != KB_OK) return st;
+    }
+    return KB_OK;
 }
 
 }  // namespace

@@ -25,6 +25,7 @@
 
 #include "kbmi_common.h"
 #include "kbmi_device.h"
+#include "kbmi_group.h"
 
 
 namespace kbmi {
@@ -288,12 +289,12 @@ __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
 // order.
 // ---------------------------------------------------------------------------
 constexpr int RS_PX = 64;                                   // start pixels per workgroup
-constexpr int RS_BINS = 1024;                               // counting-sort bins
 constexpr int RS_MAXQ = RS_PX * KB_MAX_KCAND / TK_THREADS;  // pairs per thread, at most
+static_assert(TK_THREADS == GR_THREADS, "the re-score groups its pairs by velocity");
 
 size_t rescore_lds_bytes(int k_cand) {
     const size_t np = (size_t)RS_PX * (size_t)k_cand;
-    return np * 8 + np * 4 + ((np * 2 + 7) & ~(size_t)7) + RS_BINS * 4 + 32;
+    return np * 8 + np * 4 + ((np * 2 + 7) & ~(size_t)7) + group_lds_bytes();
 }
 
 __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
@@ -304,11 +305,14 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
     extern __shared__ __align__(16) unsigned char rs_lds[];
     const int np_max = RS_PX * k_cand;
     uint64_t *s_key = reinterpret_cast<uint64_t *>(rs_lds);
+    // s_al holds each pair's velocity index until the pair is scored (by the
+    // one thread that then writes its alpha there).
     float *s_al = reinterpret_cast<float *>(rs_lds + (size_t)np_max * 8);
+    int32_t *s_vj = reinterpret_cast<int32_t *>(s_al);
     uint16_t *s_ord = reinterpret_cast<uint16_t *>(rs_lds + (size_t)np_max * 12);
     uint32_t *s_bin = reinterpret_cast<uint32_t *>(
         rs_lds + (size_t)np_max * 12 + (((size_t)np_max * 2 + 7) & ~(size_t)7));
-    uint32_t *s_tot = s_bin + RS_BINS;   // 4 wave totals, then the sum
+    uint32_t *s_tot = s_bin + GR_BINS;
 
     // Tiles are RS_PX pixels of one row (the last of a row may be shorter).
     // Workgroups reach the 8 XCDs round-robin, and XCD x walks down tile
@@ -326,68 +330,19 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
     const int npx = min(RS_PX, w - ct * RS_PX);
     const int np = npx * k_cand;
     const int t = (int)threadIdx.x;
-    const int nb = n_vel < RS_BINS ? n_vel : RS_BINS;
     const int32_t *cv = cand_vel + p0 * (int64_t)k_cand;
 
-    for (int b = t; b < RS_BINS; b += TK_THREADS) s_bin[b] = 0u;
-    __syncthreads();
-
-    // Count pairs per bin; remember each pair's bin and place within it.
-    uint32_t slot[RS_MAXQ];
-#pragma unroll
-    for (int r = 0; r < RS_MAXQ; ++r) {
-        const int q = t + r * TK_THREADS;
-        slot[r] = 0xFFFFFFFFu;
-        if (q < np) {
-            const int32_t j = cv[q];
-            // A candidate index outside the grid (not written by kb_search)
-            // is dropped: key 0 ranks below every scored candidate.
-            const bool ok = j >= 0 && j < n_vel;
-            s_key[q] = ok ? (uint64_t)j : 0ull;
-            if (ok) {
-                const uint32_t b = (uint32_t)(((int64_t)j * nb) / n_vel);
-                slot[r] = (b << 16) | atomicAdd(&s_bin[b], 1u);
-            }
-        }
-    }
-    __syncthreads();
-
-    // Exclusive scan of the bin counts: 4 bins per thread, then across lanes
-    // and waves.
-    {
-        uint32_t c4[4], run = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            c4[e] = run;
-            run += s_bin[4 * t + e];
-        }
-        const int lane = t & 63, wv = t >> 6;
-        uint32_t inc = run;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += o;
-        }
-        if (lane == 63) s_tot[wv] = inc;
-        __syncthreads();
-        uint32_t base = inc - run;
-        for (int v2 = 0; v2 < wv; ++v2) base += s_tot[v2];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) s_bin[4 * t + e] = base + c4[e];
-        if (t == TK_THREADS - 1) s_tot[4] = base + run;   // pairs to score
-    }
-    __syncthreads();
-    const int n_sorted = (int)s_tot[4];
-#pragma unroll
-    for (int r = 0; r < RS_MAXQ; ++r)
-        if (slot[r] != 0xFFFFFFFFu)
-            s_ord[s_bin[slot[r] >> 16] + (slot[r] & 0xFFFFu)] = (uint16_t)(t + r * TK_THREADS);
-    __syncthreads();
+    // Group the pairs by velocity.  A candidate index outside the grid (not
+    // written by kb_search) is dropped: key 0 ranks below every scored one.
+    const int n_sorted =
+        group_pairs_by_velocity<RS_MAXQ>(cv, np, n_vel, s_vj, s_ord, s_bin, s_tot);
+    for (int q = t; q < np; q += TK_THREADS)
+        if (s_vj[q] < 0) s_key[q] = 0ull;
 
     // Score the pairs in velocity-grouped order.
     for (int pos = t; pos < n_sorted; pos += TK_THREADS) {
         const int q = s_ord[pos];
-        const int j = (int)s_key[q];
+        const int j = s_vj[q];
         const int lp = q / k_cand;
         const int64_t p = p0 + lp;
         const int y0 = (int)(p / w), x0 = (int)(p - (int64_t)y0 * w);
@@ -416,7 +371,7 @@ __global__ __launch_bounds__(TK_THREADS) void topk_rescore_kernel(
         const float r = inv_sqrt_phi(F);
         const float v_nu = score_nu(P, F, r);
         s_key[q] = make_key(v_nu, j, c);
-        s_al[q] = score_alpha(v_nu, F, r);
+        s_al[q] = score_alpha(P, v_nu, F, r);
     }
     __syncthreads();
 
@@ -579,11 +534,13 @@ kb_status launch_search_in(const void *planes, int32_t dtype, const float *lp_sc
         const kb_status st = launch_status("inv_scale_kernel");
         if (st != KB_OK) return st;
     }
-    return launch_search(dtype, ((int)k_cand + 1) & ~1, sv, s);
+    return launch_search(dtype, km_for((int)k_cand), sv, s);
 }
 
 // Dispatch to the translation unit of (plane format, list-length group).
 kb_status launch_search(int fmt, int km, const StackView &v, hipStream_t s) {
+    if (km_index(km) < 0)
+        return fail(KB_EUNSUPPORTED, "no search compiled for list length %d", km);
     switch (fmt * kKmGroups + km_group(km)) {
 #define KB_GROUP(F, G)                                \
     case F * kKmGroups + G:                           \
@@ -599,11 +556,15 @@ kb_status launch_search(int fmt, int km, const StackView &v, hipStream_t s) {
 }
 
 kb_status launch_search_batch(int fmt, int km, const BatchJob *jobs, int n_jobs,
-                              int total_blocks, int k_cand, hipStream_t s) {
+                              int n_img_class, int k_cand, int generations, uint32_t *sync,
+                              int *grid, hipStream_t s) {
+    if (km_index(km) < 0)
+        return fail(KB_EUNSUPPORTED, "no batched search compiled for list length %d", km);
     switch (fmt * kKmGroups + km_group(km)) {
-#define KB_GROUP(F, G)                                                                    \
-    case F * kKmGroups + G:                                                               \
-        return launch_search_batch_group<F, G>(km, jobs, n_jobs, total_blocks, k_cand, s);
+#define KB_GROUP(F, G)                                                                      \
+    case F * kKmGroups + G:                                                                 \
+        return launch_search_batch_group<F, G>(km, jobs, n_jobs, n_img_class, k_cand,      \
+                                               generations, sync, grid, s);
 #define KB_FMT(F)                                                                    \
     KB_GROUP(F, 0) KB_GROUP(F, 1) KB_GROUP(F, 2) KB_GROUP(F, 3) KB_GROUP(F, 4)       \
     KB_GROUP(F, 5) KB_GROUP(F, 6) KB_GROUP(F, 7)
@@ -918,11 +879,13 @@ kb_status kb_topk(const float *psi_phi_f32, int64_t n_img, int64_t h, int64_t w,
 
 namespace {
 
-// Batch workspace: the device job descriptors, then per job its table, visiting
-// order and 16-bit inverse scales (each 256-byte aligned).
+// Batch workspace: the device job descriptors (in launch order: the jobs of
+// image-count class 0, then 1, then 2), the per-XCD counters of the three
+// launches (3 x 8 words), then per job its table, visiting order and 16-bit
+// inverse scales (each 256-byte aligned; job order as given).
 struct BatchLayout {
     std::vector<size_t> table, order, inv_scale;
-    size_t total;
+    size_t sync, total;
 };
 
 size_t round256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
@@ -930,6 +893,8 @@ size_t round256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
 bool batch_layout(const kb_job *jobs, int64_t n_jobs, BatchLayout &l) {
     if (!jobs || n_jobs < 1 || n_jobs > 4096) return false;
     size_t off = round256(sizeof(BatchJob) * static_cast<size_t>(n_jobs));
+    l.sync = off;
+    off += 256;
     l.table.resize(n_jobs);
     l.order.resize(n_jobs);
     l.inv_scale.resize(n_jobs);
@@ -946,6 +911,10 @@ bool batch_layout(const kb_job *jobs, int64_t n_jobs, BatchLayout &l) {
     l.total = off;
     return true;
 }
+
+// Image-count class of a job: the batch launches one kernel per class (one
+// load batch of 8 or 16 per velocity, or batches of 16), like kb_search.
+int image_class(int64_t n_img) { return n_img <= 8 ? 0 : (n_img <= 16 ? 1 : 2); }
 
 }  // namespace
 
@@ -966,7 +935,6 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
     if (k_cand < 1) return fail(KB_EINVAL, "k_cand must be >= 1");
     if (k_cand > KB_MAX_KCAND)
         return fail(KB_EUNSUPPORTED, "k_cand above %d is not supported", KB_MAX_KCAND);
-    int64_t total_blocks = 0;
     for (int64_t q = 0; q < n_jobs; ++q) {
         const kb_job &j = jobs[q];
         if (!j.planes || !j.cand_nu || !j.cand_alpha || !j.cand_vel || !j.cand_nobs)
@@ -982,10 +950,7 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
         if (st != KB_OK) return fail(st, "job %lld: %s", (long long)q, kb_last_error());
         if (dtype != KB_F32 && !j.lp_scale)
             return fail(KB_EINVAL, "job %lld: 16-bit planes need lp_scale", (long long)q);
-        total_blocks += (j.w + 63) / 64 * j.h;
     }
-    if (total_blocks > 2147483647LL)
-        return fail(KB_EINVAL, "batch holds more workgroups than one launch");
     BatchLayout lay;
     batch_layout(jobs, n_jobs, lay);
     if (!workspace) return fail(KB_EINVAL, "workspace must be non-null");
@@ -994,37 +959,76 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
     if (workspace_bytes < lay.total)
         return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", lay.total, workspace_bytes);
 
-    // Stage descriptors and tables on the host, then one copy.
+    // Work items of each class's persistent launch.  A job of float32 planes
+    // large enough for the paced block order (as kb_search chooses it) starts
+    // at a generation boundary and takes its whole block sequence; the others
+    // are packed densely, tile after tile.
+    const int kc = (int)k_cand;
+    const int km = km_for(kc);
+    hipStream_t s = (hipStream_t)stream;
+    int grid[3] = {0, 0, 0}, count[3] = {0, 0, 0}, first[3] = {0, 0, 0};
+    int64_t gens[3] = {0, 0, 0};
+    std::vector<int> launch_order;
+    for (int c = 0; c < 3; ++c) {
+        first[c] = (int)launch_order.size();
+        for (int64_t q = 0; q < n_jobs; ++q)
+            if (image_class(jobs[q].n_img) == c) launch_order.push_back((int)q);
+        count[c] = (int)launch_order.size() - first[c];
+        if (count[c] > 0) {
+            kb_status st = launch_search_batch(dtype, km, nullptr, 0, c, kc, 0, nullptr,
+                                               &grid[c], s);
+            if (st != KB_OK) return st;
+        }
+    }
     char *ws = static_cast<char *>(workspace);
     std::vector<char> host(lay.total, 0);
     BatchJob *desc = reinterpret_cast<BatchJob *>(host.data());
-    int block_begin = 0;
-    for (int64_t q = 0; q < n_jobs; ++q) {
-        const kb_job &j = jobs[q];
-        gather_table(j.t, j.n_img, j.vel, j.n_vel, j.h, j.w, dtype == KB_F32 ? 8 : 4, true,
-                     reinterpret_cast<GatherEntry *>(host.data() + lay.table[q]),
-                     reinterpret_cast<int32_t *>(host.data() + lay.order[q]));
-        const int64_t stride = table_stride(j.n_img);
-        BatchJob &d = desc[q];
-        d.planes = j.planes;
-        d.inv_scale = reinterpret_cast<const float2 *>(ws + lay.inv_scale[q]);
-        d.disp = reinterpret_cast<const GatherEntry *>(ws + lay.table[q]);
-        d.vel_index = reinterpret_cast<const int32_t *>(ws + lay.order[q]);
-        d.cand_nu = j.cand_nu;
-        d.cand_alpha = j.cand_alpha;
-        d.cand_vel = j.cand_vel;
-        d.cand_nobs = j.cand_nobs;
-        d.n_img = (int)j.n_img;
-        d.h = (int)j.h;
-        d.w = (int)j.w;
-        d.disp_stride = (int)stride;
-        d.n_vel = (int)j.n_vel;
-        d.nseg = (int)((j.w + 63) / 64);
-        d.strip = d.nseg < KBMI_STRIP_TILES ? d.nseg : KBMI_STRIP_TILES;
-        d.block_begin = block_begin;
-        block_begin += d.nseg * d.h;
+    for (int c = 0; c < 3; ++c) {
+        int64_t cursor = 0;
+        const int g = grid[c];
+        for (int pos = first[c]; pos < first[c] + count[c]; ++pos) {
+            const int q = launch_order[pos];
+            const kb_job &j = jobs[q];
+            gather_table(j.t, j.n_img, j.vel, j.n_vel, j.h, j.w, dtype == KB_F32 ? 8 : 4, true,
+                         reinterpret_cast<GatherEntry *>(host.data() + lay.table[q]),
+                         reinterpret_cast<int32_t *>(host.data() + lay.order[q]));
+            BatchJob &d = desc[pos];
+            d.planes = j.planes;
+            d.inv_scale = reinterpret_cast<const float2 *>(ws + lay.inv_scale[q]);
+            d.disp = reinterpret_cast<const GatherEntry *>(ws + lay.table[q]);
+            d.vel_index = reinterpret_cast<const int32_t *>(ws + lay.order[q]);
+            d.cand_nu = j.cand_nu;
+            d.cand_alpha = j.cand_alpha;
+            d.cand_vel = j.cand_vel;
+            d.cand_nobs = j.cand_nobs;
+            d.n_img = (int)j.n_img;
+            d.h = (int)j.h;
+            d.w = (int)j.w;
+            d.disp_stride = (int)table_stride(j.n_img);
+            d.n_vel = (int)j.n_vel;
+            d.nseg = (int)((j.w + 63) / 64);
+            d.strip = d.nseg < KBMI_STRIP_TILES ? d.nseg : KBMI_STRIP_TILES;
+            const int64_t tiles = (int64_t)d.nseg * j.h;
+            const bool block = KBMI_PERSIST_BS > 0 && dtype == KB_F32 &&
+                               (g / 8) % KBMI_PERSIST_BS == 0 && tiles >= 4 * (int64_t)g;
+            d.dense = block ? 0 : 1;
+            d.bs = KBMI_PERSIST_BS > 0 ? KBMI_PERSIST_BS : 1;
+            d.brows = (g / 8) / d.bs;
+            d.nbc = (d.nseg + d.bs - 1) / d.bs;
+            d.nbr = (d.h + d.brows - 1) / d.brows;
+            if (block) {
+                cursor = (cursor + g - 1) / g * g;
+                d.item_begin = (int)std::min<int64_t>(cursor, 2147483647LL);
+                cursor += (int64_t)((d.nbc + 7) / 8) * d.nbr * g;
+            } else {
+                d.item_begin = (int)std::min<int64_t>(cursor, 2147483647LL);
+                cursor += tiles;
+            }
+            if (cursor + g > 2147483647LL)
+                return fail(KB_EINVAL, "batch holds more work items than one launch");
+        }
+        gens[c] = g > 0 ? (cursor + g - 1) / g : 0;
     }
-    hipStream_t s = (hipStream_t)stream;
     kb_status up = staged_copy(ws, host.data(), host.size(), s);
     if (up != KB_OK) return up;
     if (dtype != KB_F32) {
@@ -1037,9 +1041,15 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
             if (st != KB_OK) return st;
         }
     }
-    const int kc = (int)k_cand;
-    const BatchJob *dj = reinterpret_cast<const BatchJob *>(ws);
-    return launch_search_batch(dtype, (kc + 1) & ~1, dj, (int)n_jobs, (int)total_blocks, kc, s);
+    for (int c = 0; c < 3; ++c) {
+        if (count[c] == 0) continue;
+        const BatchJob *dj = reinterpret_cast<const BatchJob *>(ws) + first[c];
+        uint32_t *sync = reinterpret_cast<uint32_t *>(ws + lay.sync) + 8 * c;
+        kb_status st = launch_search_batch(dtype, km, dj, count[c], c, kc, (int)gens[c], sync,
+                                           &grid[c], s);
+        if (st != KB_OK) return st;
+    }
+    return KB_OK;
 }
 
 }  // extern "C"

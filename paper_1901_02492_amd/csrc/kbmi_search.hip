@@ -46,15 +46,16 @@ int resident_workgroups() {
     return cached[dev];
 }
 
-template <int KM, int NB>
+template <int KM, int NB, bool MB>
 kb_status launch_one(const StackView &v, hipStream_t s) {
     constexpr int PB = KBMI_QUEUE;
     static_assert(NB == 8 || NB == 16, "table rows are padded for batches of 8 or 16");
     // The persistent order pays where gathers dominate (float32 planes); the
     // 16-bit search keeps the super-strip order, which measured faster.
     if (KBMI_PERSIST_BS > 0 && KBMI_FMT == KB_F32) {
-        auto kernel = search_persistent_kernel<KM, NB, PB, KBMI_FMT>;
-        const int grid = resident_workgroups<search_persistent_kernel<KM, NB, PB, KBMI_FMT>>();
+        auto kernel = search_persistent_kernel<KM, NB, PB, KBMI_FMT, MB>;
+        const int grid =
+            resident_workgroups<search_persistent_kernel<KM, NB, PB, KBMI_FMT, MB>>();
         const int nseg = (v.w + 63) / 64;
         const int per_xcd = grid / 8;
         // Worth it only when the frame holds several generations of blocks.
@@ -80,7 +81,7 @@ kb_status launch_one(const StackView &v, hipStream_t s) {
         }
     }
     const TileMap tm = tile_map(v.w, v.h);
-    hipLaunchKernelGGL((search_kernel<KM, NB, PB, KBMI_FMT>), dim3(tm.nblocks), dim3(64), 0, s,
+    hipLaunchKernelGGL((search_kernel<KM, NB, PB, KBMI_FMT, MB>), dim3(tm.nblocks), dim3(64), 0, s,
                        v.planes, v.inv_scale, v.n_img, v.h, v.w, v.disp, v.disp_stride,
                        v.vel_index, v.n_vel, v.k_cand, tm, v.cand_nu, v.cand_alpha, v.cand_vel,
                        v.cand_nobs, v.row_lo, v.row_hi);
@@ -89,16 +90,41 @@ kb_status launch_one(const StackView &v, hipStream_t s) {
 
 template <int KM>
 kb_status launch_km(const StackView &v, hipStream_t s) {
-    return v.n_img <= 8 ? launch_one<KM, 8>(v, s) : launch_one<KM, 16>(v, s);
+    // One batch of 8 or 16 loads per velocity, or batches of 16 (MB).
+    if (v.n_img <= 8) return launch_one<KM, 8, false>(v, s);
+    if (v.n_img <= 16) return launch_one<KM, 16, false>(v, s);
+    return launch_one<KM, 16, true>(v, s);
+}
+
+template <int KM, int NB, bool MB>
+kb_status launch_batch_one(const BatchJob *jobs, int n_jobs, int k_cand, int generations,
+                           uint32_t *sync, int *grid, hipStream_t s) {
+    constexpr int PB = KBMI_QUEUE;
+    auto kernel = search_batch_kernel<KM, NB, PB, KBMI_FMT, MB>;
+    const int g = resident_workgroups<search_batch_kernel<KM, NB, PB, KBMI_FMT, MB>>();
+    if (g < 8 || g % 8 != 0)
+        return fail(KB_EDEVICE, "batched search: no persistent grid for this device (%d)", g);
+    if (!jobs) {
+        *grid = g;
+        return KB_OK;
+    }
+    if (*grid != g) return fail(KB_EDEVICE, "batched search: grid changed (%d, %d)", *grid, g);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, sync, 8);
+    kb_status st = launch_status("zero_words_kernel");
+    if (st != KB_OK) return st;
+    hipLaunchKernelGGL(kernel, dim3(g), dim3(64), 0, s, jobs, n_jobs, generations,
+                       KBMI_PERSIST_SPIN, k_cand, sync);
+    return launch_status("search_batch_kernel");
 }
 
 template <int KM>
-kb_status launch_batch_km(const BatchJob *jobs, int n_jobs, int total_blocks, int k_cand,
-                          hipStream_t s) {
-    constexpr int PB = KBMI_QUEUE;
-    hipLaunchKernelGGL((search_batch_kernel<KM, PB, KBMI_FMT>), dim3(total_blocks), dim3(64), 0, s,
-                       jobs, n_jobs, total_blocks, k_cand);
-    return launch_status("search_batch_kernel");
+kb_status launch_batch_km(const BatchJob *jobs, int n_jobs, int n_img_class, int k_cand,
+                          int generations, uint32_t *sync, int *grid, hipStream_t s) {
+    if (n_img_class == 0)
+        return launch_batch_one<KM, 8, false>(jobs, n_jobs, k_cand, generations, sync, grid, s);
+    if (n_img_class == 1)
+        return launch_batch_one<KM, 16, false>(jobs, n_jobs, k_cand, generations, sync, grid, s);
+    return launch_batch_one<KM, 16, true>(jobs, n_jobs, k_cand, generations, sync, grid, s);
 }
 
 // List lengths of this translation unit's group are compiled; the others are
@@ -110,10 +136,10 @@ kb_status launch_in_group(const StackView &v, hipStream_t s) {
 }
 
 template <int K>
-kb_status launch_batch_in_group(const BatchJob *jobs, int n_jobs, int total_blocks, int k_cand,
-                                hipStream_t s) {
+kb_status launch_batch_in_group(const BatchJob *jobs, int n_jobs, int n_img_class, int k_cand,
+                                int generations, uint32_t *sync, int *grid, hipStream_t s) {
     if constexpr (km_group(K) == KBMI_GROUP)
-        return launch_batch_km<K>(jobs, n_jobs, total_blocks, k_cand, s);
+        return launch_batch_km<K>(jobs, n_jobs, n_img_class, k_cand, generations, sync, grid, s);
     else return fail(KB_EUNSUPPORTED, "list length %d is not compiled in this group", K);
 }
 
@@ -133,12 +159,15 @@ kb_status launch_search_group<KBMI_FMT, KBMI_GROUP>(int km, const StackView &v, 
 
 template <>
 kb_status launch_search_batch_group<KBMI_FMT, KBMI_GROUP>(int km, const BatchJob *jobs,
-                                                           int n_jobs, int total_blocks,
-                                                           int k_cand, hipStream_t s) {
+                                                           int n_jobs, int n_img_class,
+                                                           int k_cand, int generations,
+                                                           uint32_t *sync, int *grid,
+                                                           hipStream_t s) {
     switch (km) {
-#define KB_CASE(K) \
-    case K:        \
-        return launch_batch_in_group<K>(jobs, n_jobs, total_blocks, k_cand, s);
+#define KB_CASE(K)                                                                     \
+    case K:                                                                            \
+        return launch_batch_in_group<K>(jobs, n_jobs, n_img_class, k_cand, generations, \
+                                        sync, grid, s);
         KB_SEARCH_KM_LIST(KB_CASE)
 #undef KB_CASE
     }

@@ -2,11 +2,11 @@
 // second paragraph: the remaining candidates' coadded stamps are kept when
 // their central moments resemble those of a Gaussian centred on the stamp).
 //
-// One thread per candidate.  Its displacements are computed once into
-// registers (floor(v * tau + 0.5) in double, as everywhere else); then, for
-// each stamp pixel in row-major order, the science-image pixels of the kept
-// images are averaged in image order in double, and the raw moments about the
-// stamp centre are accumulated in the same pass.  Every product, sum and
+// One wave per candidate.  Its displacements are computed once
+// (floor(v * tau + 0.5) in double, as everywhere else); each stamp pixel (one
+// lane) averages the science-image pixels of the kept images in image order
+// in double, and the raw moments about the stamp centre are then accumulated
+// over the stamp in row-major order.  Every product, sum and
 // quotient is a separately rounded IEEE double operation in a fixed order, so
 // the outputs are a reproducible function of the inputs:
 //   S(u, v) = (sum_i img_i) / n(u, v)  over valid in-frame pixels (0 if none)
@@ -26,7 +26,8 @@
 namespace kbmi {
 namespace {
 
-constexpr int ST_THREADS = 128;
+constexpr int ST_WAVES = 4;                  // candidates (one wave each) per workgroup
+constexpr int ST_THREADS = 64 * ST_WAVES;
 
 // floor(v * tau + 0.5) without the clamp of the search's table: a stamp
 // reaches R pixels past its centre, so an offset beyond the frame must stay
@@ -40,6 +41,12 @@ struct StampLimits {
     double max_offset, max_m11, m2_min, m2_max;
 };
 
+// One wave per candidate.  The lanes cover the stamp's pixels (row-major,
+// 64 at a time), so the lanes of one load read runs of adjacent pixels of one
+// image row; each lane sums its pixel over the kept images in image order.
+// The stamp goes to LDS, and lane 0 takes the moments in row-major order:
+// every value is the same sequence of double operations as one thread per
+// candidate walking the stamp.
 template <int NB>
 __global__ __launch_bounds__(ST_THREADS) void stamp_kernel(
     const float *__restrict__ img, const float *__restrict__ var,
@@ -48,54 +55,69 @@ __global__ __launch_bounds__(ST_THREADS) void stamp_kernel(
     const uint64_t *__restrict__ drop, int64_t n_cand, int R, StampLimits lim,
     float *__restrict__ stamps, double *__restrict__ moments, uint8_t *__restrict__ pass) {
 #pragma clang fp contract(off)
-    const int64_t c = (int64_t)blockIdx.x * ST_THREADS + threadIdx.x;
-    if (c >= n_cand) return;
-    const kb_hit hit = cand[c];
+    extern __shared__ double s_stamp[];   // [ST_WAVES][side * side]
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * ST_WAVES + wave;
+    const bool live = c < n_cand;
     const int side = 2 * R + 1;
-    const bool ok_vel = hit.vel >= 0 && hit.vel < n_vel;
+    const int npix = side * side;
+    double *S_l = s_stamp + (size_t)wave * npix;
+    kb_hit hit{};
+    bool ok_vel = false;
+    if (live) {
+        hit = cand[c];
+        ok_vel = hit.vel >= 0 && hit.vel < n_vel;
+    }
     int dx[NB], dy[NB];
     uint64_t use = 0;   // images this candidate may use
-    if (ok_vel) {
-        const double2 vj = vels[hit.vel];
-        const uint64_t dropped = drop ? drop[c] : 0;
+    {
+        const double2 vj = ok_vel ? vels[hit.vel] : make_double2(0.0, 0.0);
+        const uint64_t dropped = (live && drop) ? drop[c] : 0;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             dx[i] = 0;
             dy[i] = 0;
-            if (i < n_img) {
+            if (ok_vel && i < n_img) {
                 dx[i] = stamp_offset(vj.x, tau[i]);
                 dy[i] = stamp_offset(vj.y, tau[i]);
                 if (!((dropped >> i) & 1u)) use |= uint64_t(1) << i;
             }
         }
     }
+    for (int e = lane; e < npix; e += 64) {
+        const int a = e / side, b = e - a * side;
+        double acc = 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if ((use >> i) & 1u) {
+                const int64_t yy = (int64_t)hit.y + dy[i] + (a - R);
+                const int64_t xx = (int64_t)hit.x + dx[i] + (b - R);
+                if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
+                    const size_t p = ((size_t)i * h + yy) * (size_t)w + xx;
+                    const float im = img[p];
+                    const float va = var[p];
+                    const bool valid = (mask == nullptr || mask[p] == 0) && isfinite(im) &&
+                                       isfinite(va) && va > 0.f;
+                    if (valid) {
+                        acc = acc + (double)im;
+                        ++cnt;
+                    }
+                }
+            }
+        }
+        const double S = cnt > 0 ? acc / (double)cnt : 0.0;   // exact int -> double
+        S_l[e] = S;
+        if (live && stamps) stamps[c * npix + e] = (float)S;
+    }
+    __syncthreads();
+    if (!live || lane != 0) return;
     double M00 = 0.0, M10 = 0.0, M01 = 0.0, M20 = 0.0, M02 = 0.0, M11 = 0.0;
     for (int a = 0; a < side; ++a) {
         const double v = (double)(a - R);
         for (int b = 0; b < side; ++b) {
             const double u = (double)(b - R);
-            double acc = 0.0;
-            int cnt = 0;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                if ((use >> i) & 1u) {
-                    const int64_t yy = (int64_t)hit.y + dy[i] + (a - R);
-                    const int64_t xx = (int64_t)hit.x + dx[i] + (b - R);
-                    if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
-                        const size_t p = ((size_t)i * h + yy) * (size_t)w + xx;
-                        const float im = img[p];
-                        const float va = var[p];
-                        const bool valid = (mask == nullptr || mask[p] == 0) && isfinite(im) &&
-                                           isfinite(va) && va > 0.f;
-                        if (valid) {
-                            acc = acc + (double)im;
-                            ++cnt;
-                        }
-                    }
-                }
-            }
-            const double S = cnt > 0 ? acc / (double)cnt : 0.0;   // exact int -> double
-            if (stamps) stamps[c * side * side + a * side + b] = (float)S;
+            const double S = S_l[a * side + b];
             M00 = M00 + S;
             M10 = M10 + u * S;
             M01 = M01 + v * S;
@@ -130,8 +152,9 @@ kb_status launch_stamps(const float *img, const float *var, const uint8_t *mask,
                         const kb_hit *cand, const uint64_t *drop, int64_t n_cand, int R,
                         StampLimits lim, float *stamps, double *moments, uint8_t *pass,
                         hipStream_t s) {
-    const int64_t blocks = (n_cand + ST_THREADS - 1) / ST_THREADS;
-    hipLaunchKernelGGL(stamp_kernel<NB>, dim3((unsigned)blocks), dim3(ST_THREADS), 0, s, img, var,
+    const int64_t blocks = (n_cand + ST_WAVES - 1) / ST_WAVES;
+    const size_t lds = (size_t)ST_WAVES * (2 * R + 1) * (2 * R + 1) * sizeof(double);
+    hipLaunchKernelGGL(stamp_kernel<NB>, dim3((unsigned)blocks), dim3(ST_THREADS), lds, s, img, var,
                        mask, n_img, h, w, tau, vels, n_vel, cand, drop, n_cand, R, lim, stamps,
                        moments, pass);
     return launch_status("stamp_kernel");
@@ -166,7 +189,7 @@ kb_status kb_stamps(const float *img, const float *var, const uint8_t *mask, int
                     (int)radius);
     if (std::isnan(max_offset) || std::isnan(max_m11) || std::isnan(m2_min) || std::isnan(m2_max))
         return fail(KB_EINVAL, "filter bounds must not be NaN");
-    if (n_cand > (int64_t)ST_THREADS * 2147483647LL)
+    if (n_cand > (int64_t)ST_WAVES * 2147483647LL)
         return fail(KB_EINVAL, "too many candidates for one launch");
     st = check_times_velocities(t, n_img, vel, n_vel);
     if (st != KB_OK) return st;

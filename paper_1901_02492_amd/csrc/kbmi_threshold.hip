@@ -7,11 +7,11 @@
 //                            (DBSCAN with min_samples = 1, Sec. 3.3) by
 //                            lock-free union-find, and each group's best hit
 //
-// The threshold search gathers and scores exactly as the top-k search does
-// (same table, loads, image order and score functions), so a hit's nu, alpha
+// The threshold search runs the top-k search's own gathers (visit_velocities:
+// same table, loads, image order) and score functions, so a hit's nu, alpha
 // and n_obs are bitwise the values the top-k path gives that trajectory.  It
 // keeps no list, so it needs few registers; it runs in the top-k search's
-// paced persistent order with two velocities' gathers in flight.
+// paced persistent order with two batches' gathers in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,7 +32,10 @@ constexpr int TH_STRIP = 4;        // tiles per strip of the tile order
 #define KBMI_TH_PERSIST 1   // threshold search: paced persistent order (float32 search's)
 #endif
 
-// One tile: 64 adjacent start pixels of one row, every velocity.
+// One tile: 64 adjacent start pixels of one row, every velocity, with the
+// top-k search's gathers (visit_velocities); each trajectory is scored and
+// appended if nu >= nu_min: one atomic per wave reserves the wave's slots.
+template <bool MB, bool INTERIOR>
 __device__ __forceinline__ void threshold_tile(
     const float2 *__restrict__ planes, int n_img, int h, int w,
     const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
@@ -40,39 +43,7 @@ __device__ __forceinline__ void threshold_tile(
     unsigned long long *__restrict__ n_hits) {
     const int lane = (int)threadIdx.x;
     const int x0 = seg * 64 + lane;
-    const uint32_t row_bytes = (uint32_t)w * 8u;
-    const uint64_t row0 = reinterpret_cast<uint64_t>(planes) + (uint64_t)row * row_bytes;
-    const const_i32 *visit = (const const_i32 *)(const void *)vel_index;
     const uint64_t below = (uint64_t(1) << lane) - 1;
-
-    auto fetch = [&](int jj, int i0, i32x4(&e)[TH_NB]) {
-        const const_i32x4 *t4 =
-            (const const_i32x4 *)(const void *)(disp + (size_t)jj * disp_stride + i0);
-#pragma unroll
-        for (int b = 0; b < TH_NB; ++b) e[b] = t4[b];
-    };
-    // Rows outside the frame (padding entries included) get a zero-length
-    // buffer: the load returns 0 without an access.
-    auto issue = [&](const i32x4(&e)[TH_NB], u32x2(&v)[TH_NB]) {
-#pragma unroll
-        for (int b = 0; b < TH_NB; ++b) {
-            const int yy = row + e[b].y;
-            const bool in_rows = (unsigned)yy < (unsigned)h;
-            const uint64_t off = ((uint64_t)(uint32_t)e[b].w << 32) | (uint32_t)e[b].z;
-            const i32x4 rs = buffer_words(row0 + off, in_rows ? row_bytes : 0u);
-            v[b] = raw_load_b64(rs, (x0 + e[b].x) * 8, 0, 0);
-        }
-    };
-    auto accumulate = [&](const u32x2(&v)[TH_NB], float &P, float &F, uint32_t &c) {
-#pragma unroll
-        for (int b = 0; b < TH_NB; ++b) {
-            P += __uint_as_float(v[b].x);
-            F += __uint_as_float(v[b].y);
-            c += min(v[b].y, 1u);
-        }
-    };
-    // Score one trajectory and append it if nu >= nu_min: one atomic per
-    // wave reserves the wave's slots in the list.
     auto finish = [&](int j, float P, float F, uint32_t c) {
         const float r = inv_sqrt_phi(F);
         const float nu = score_nu(P, F, r);
@@ -90,92 +61,58 @@ __device__ __forceinline__ void threshold_tile(
                 hit.y = row;
                 hit.vel = j;
                 hit.nu = nu;
-                hit.alpha = score_alpha(nu, F, r);
+                hit.alpha = score_alpha(P, nu, F, r);
                 hit.nobs = (int16_t)c;
                 hit.reserved = 0;
                 hits[idx] = hit;
             }
         }
     };
-
-    if (n_img <= TH_NB) {
-        // Two velocities in flight: the gathers of visit jj+1 are issued
-        // before visit jj is summed and scored; a visit past the end repeats
-        // the last row and is never scored.
-        i32x4 e[TH_NB];
-        u32x2 va[TH_NB], vb[TH_NB];
-        const int last = n_vel - 1;
-        fetch(0, 0, e);
-        issue(e, va);
-        int j_cur = visit[0];
-        int nxt = last < 1 ? last : 1;
-        fetch(nxt, 0, e);
-        int j_nxt = visit[nxt];
-        auto step = [&](int jj, u32x2(&cur)[TH_NB], u32x2(&ahead)[TH_NB]) {
-            issue(e, ahead);
-            __builtin_amdgcn_sched_barrier(0);
-            const int n2 = jj + 2 < last ? jj + 2 : last;
-            fetch(n2, 0, e);
-            const int j2 = visit[n2];
-            __builtin_amdgcn_sched_barrier(0);
-            float P = 0.f, F = 0.f;
-            uint32_t c = 0;
-            accumulate(cur, P, F, c);
-            finish(j_cur, P, F, c);
-            j_cur = j_nxt;
-            j_nxt = j2;
-        };
-        int jj = 0;
-        for (; jj + 1 < n_vel; jj += 2) {
-            step(jj, va, vb);
-            step(jj + 1, vb, va);
-        }
-        if (jj < n_vel) step(jj, va, vb);
-    } else {
-        for (int jj = 0; jj < n_vel; ++jj) {
-            float P = 0.f, F = 0.f;
-            uint32_t c = 0;
-            for (int i0 = 0; i0 < n_img; i0 += TH_NB) {
-                i32x4 e[TH_NB];
-                fetch(jj, i0, e);
-                u32x2 v[TH_NB];
-                issue(e, v);
-                accumulate(v, P, F, c);
-            }
-            finish(visit[jj], P, F, c);
-        }
-    }
+    visit_velocities<TH_NB, KB_F32, true, true, MB, INTERIOR, false>(
+        nullptr, planes, nullptr, n_img, h, w, disp, disp_stride, vel_index, n_vel, row, seg,
+        finish);
 }
 
 // Strip tile order, one wave per tile.
+template <bool MB>
 __global__ __launch_bounds__(64) void search_threshold_kernel(
     const float2 *__restrict__ planes, int n_img, int h, int w,
     const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
     int n_vel, int nseg, int ntiles, float nu_min, kb_hit *__restrict__ hits, uint64_t cap,
-    unsigned long long *__restrict__ n_hits) {
+    unsigned long long *__restrict__ n_hits, int row_lo, int row_hi) {
     int row, seg;
     strip_tile(xcd_remap((int)blockIdx.x, ntiles), nseg, h, TH_STRIP, row, seg);
-    threshold_tile(planes, n_img, h, w, disp, disp_stride, vel_index, n_vel, row, seg, nu_min,
-                   hits, cap, n_hits);
+    if (KBMI_INTERIOR && row >= row_lo && row < row_hi)
+        threshold_tile<MB, true>(planes, n_img, h, w, disp, disp_stride, vel_index, n_vel, row,
+                                 seg, nu_min, hits, cap, n_hits);
+    else
+        threshold_tile<MB, false>(planes, n_img, h, w, disp, disp_stride, vel_index, n_vel, row,
+                                  seg, nu_min, hits, cap, n_hits);
 }
 
 // The paced persistent order of the float32 top-k search: per generation each
 // XCD covers one block of start pixels and its waves wait (a bounded time) for
 // each other at the end of the generation, so that their gathers share the
 // XCD's L2.  The wait only shapes timing.
+template <bool MB>
 __global__ __launch_bounds__(64) void search_threshold_persistent_kernel(
     const float2 *__restrict__ planes, int n_img, int h, int w,
     const GatherEntry *__restrict__ disp, int disp_stride, const int32_t *__restrict__ vel_index,
     int n_vel, PersistMap pm, float nu_min, kb_hit *__restrict__ hits, uint64_t cap,
-    unsigned long long *__restrict__ n_hits, uint32_t *sync) {
+    unsigned long long *__restrict__ n_hits, uint32_t *sync, int row_lo, int row_hi) {
     uint32_t *xcd_count = sync + (blockIdx.x & 7);
     const uint32_t per_xcd = gridDim.x >> 3;
     int spin = pm.spin;
     for (int gen = 0; gen < pm.generations; ++gen) {
         int row, seg;
-        if (pm.map(gen, (int)blockIdx.x, row, seg))
-            threshold_tile(planes, n_img, h, w, disp, disp_stride, vel_index, n_vel, row, seg,
-                           nu_min, hits, cap, n_hits);
+        if (pm.map(gen, (int)blockIdx.x, row, seg)) {
+            if (KBMI_INTERIOR && row >= row_lo && row < row_hi)
+                threshold_tile<MB, true>(planes, n_img, h, w, disp, disp_stride, vel_index,
+                                         n_vel, row, seg, nu_min, hits, cap, n_hits);
+            else
+                threshold_tile<MB, false>(planes, n_img, h, w, disp, disp_stride, vel_index,
+                                          n_vel, row, seg, nu_min, hits, cap, n_hits);
+        }
         if (threadIdx.x == 0)
             __hip_atomic_fetch_add(xcd_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t target = (uint32_t)(gen + 1) * per_xcd;
@@ -190,6 +127,7 @@ __global__ __launch_bounds__(64) void search_threshold_persistent_kernel(
     }
 }
 
+template <bool MB>
 int threshold_grid() {
     static int cached[64] = {};
     int dev = 0;
@@ -197,7 +135,7 @@ int threshold_grid() {
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, search_threshold_persistent_kernel, 64, 0) != hipSuccess ||
+                &per_cu, search_threshold_persistent_kernel<MB>, 64, 0) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
         cached[dev] = std::min(per_cu, KBMI_PERSIST_PER_CU) * cus;
@@ -216,7 +154,7 @@ __global__ void zero_u64_kernel(unsigned long long *p) {
 // a smaller index, so the loop makes progress and ends.  The root of each tree
 // is therefore the smallest index of its component.
 // ---------------------------------------------------------------------------
-constexpr int CL_TILE = 256;
+constexpr int CL_THREADS = 256;
 
 __device__ inline int cl_load(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -258,45 +196,125 @@ __global__ void cl_init_kernel(int32_t *parent, uint32_t *best_nu, uint64_t *bes
     }
 }
 
-// Block (bx, by) compares the hits of tile by with those of tile bx >= by;
-// pair (i, j), i < j, is joined when d2 <= eps2 with
-// d2 = ((dx*dx + dy*dy) + du*du) + dv*dv in double, u = s * vx, v = s * vy.
-// A hit whose velocity index is outside the grid gets NaN coordinates, which
-// compare false with everything: it stays a group of its own.
+// Pairs are found through a grid of cells of side c = eps (1 + 2^-20) over
+// the four coordinates (x, y, u, v), u = s * vx, v = s * vy: two hits within
+// distance eps differ by at most eps in every coordinate, so their cells
+// differ by at most one in every coordinate, and each hit only meets the hits
+// of its own and the 80 neighbouring cells.  The cells sit in an
+// open-addressing hash table (cell key -> list of the cell's hits).  Pair
+// (i, j), i < j, is joined when d2 <= eps2 with
+// d2 = ((dx*dx + dy*dy) + du*du) + dv*dv in double.  A hit whose velocity
+// index is outside the grid gets no cell: it stays a group of its own.
 __device__ inline double2 cl_vel(const double2 *vel, int n_vel, int j) {
     return (unsigned)j < (unsigned)n_vel ? vel[j] : make_double2(NAN, NAN);
 }
 
-__global__ __launch_bounds__(CL_TILE) void cl_pairs_kernel(const kb_hit *__restrict__ hits, int n,
-                                                         const double2 *__restrict__ vel,
-                                                         int n_vel, double s, double eps2,
-                                                         int32_t *parent) {
+constexpr uint64_t kEmptyCell = ~0ull;
+
+__device__ inline int64_t cl_cell(double coord, double inv_c) {
 #pragma clang fp contract(off)
-    const int ti = (int)blockIdx.y, tj = (int)blockIdx.x;
-    if (tj < ti) return;
-    __shared__ double sx[CL_TILE], sy[CL_TILE], su[CL_TILE], sv[CL_TILE];
-    const int jl = tj * CL_TILE + (int)threadIdx.x;
-    if (jl < n) {
-        const kb_hit hj = hits[jl];
-        const double2 vj = cl_vel(vel, n_vel, hj.vel);
-        sx[threadIdx.x] = (double)hj.x;
-        sy[threadIdx.x] = (double)hj.y;
-        su[threadIdx.x] = s * vj.x;
-        sv[threadIdx.x] = s * vj.y;
+    const double q = floor(coord * inv_c);
+    return (int64_t)fmin(fmax(q, -4.0e18), 4.0e18);
+}
+
+// 64-bit key of cell (a, b, c, d) (a finalising mix of a packed sum; distinct
+// cells may share a key, which only adds hits whose distance is then tested).
+__device__ inline uint64_t cl_cell_key(int64_t a, int64_t b, int64_t c, int64_t d) {
+    uint64_t z = (uint64_t)a * 0x9E3779B97F4A7C15ull + (uint64_t)b * 0xC2B2AE3D27D4EB4Full +
+                 (uint64_t)c * 0x165667B19E3779F9ull + (uint64_t)d * 0xD6E8FEB86659FD93ull;
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z == kEmptyCell ? kEmptyCell - 1 : z;
+}
+
+struct ClHit {
+    double x, y, u, v;
+    bool ok;
+};
+
+__device__ inline ClHit cl_hit(const kb_hit *hits, const double2 *vel, int n_vel, double s,
+                               int i) {
+#pragma clang fp contract(off)
+    const kb_hit h = hits[i];
+    const double2 vj = cl_vel(vel, n_vel, h.vel);
+    ClHit r;
+    r.x = (double)h.x;
+    r.y = (double)h.y;
+    r.u = s * vj.x;
+    r.v = s * vj.y;
+    r.ok = (unsigned)h.vel < (unsigned)n_vel;
+    return r;
+}
+
+__global__ void cl_table_init_kernel(uint64_t *table_key, int32_t *table_head, int64_t slots) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slots;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        table_key[i] = kEmptyCell;
+        table_head[i] = -1;
     }
-    __syncthreads();
-    const int i = ti * CL_TILE + (int)threadIdx.x;
+}
+
+// Hit i joins the list of its cell (pushed at the head; the lists are read by
+// the next kernel only).
+__global__ __launch_bounds__(CL_THREADS) void cl_insert_kernel(
+    const kb_hit *__restrict__ hits, int n, const double2 *__restrict__ vel, int n_vel, double s,
+    double inv_c, uint64_t *table_key, int32_t *table_head, uint64_t mask,
+    int32_t *__restrict__ next) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
-    const kb_hit hi = hits[i];
-    const double2 vi = cl_vel(vel, n_vel, hi.vel);
-    const double xi = (double)hi.x, yi = (double)hi.y, ui = s * vi.x, vv = s * vi.y;
-    const int jn = min(CL_TILE, n - tj * CL_TILE);
-    for (int q = 0; q < jn; ++q) {
-        const int j = tj * CL_TILE + q;
-        if (j <= i) continue;
-        const double dx = xi - sx[q], dy = yi - sy[q], du = ui - su[q], dv = vv - sv[q];
-        const double d2 = ((dx * dx + dy * dy) + du * du) + dv * dv;
-        if (d2 <= eps2) cl_unite(parent, i, j);
+    const ClHit h = cl_hit(hits, vel, n_vel, s, i);
+    next[i] = -1;
+    if (!h.ok) return;
+    const uint64_t key = cl_cell_key(cl_cell(h.x, inv_c), cl_cell(h.y, inv_c),
+                                     cl_cell(h.u, inv_c), cl_cell(h.v, inv_c));
+    uint64_t slot = key & mask;
+    for (;;) {
+        const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long *>(table_key + slot),
+                                        (unsigned long long)kEmptyCell,
+                                        (unsigned long long)key);
+        if (prev == kEmptyCell || prev == key) {
+            next[i] = atomicExch(table_head + slot, i);
+            return;
+        }
+        slot = (slot + 1) & mask;   // the table has at least twice as many slots as hits
+    }
+}
+
+__global__ __launch_bounds__(CL_THREADS) void cl_grid_pairs_kernel(
+    const kb_hit *__restrict__ hits, int n, const double2 *__restrict__ vel, int n_vel, double s,
+    double inv_c, double eps2, const uint64_t *__restrict__ table_key,
+    const int32_t *__restrict__ table_head, uint64_t mask, const int32_t *__restrict__ next,
+    int32_t *parent) {
+#pragma clang fp contract(off)
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const ClHit hi = cl_hit(hits, vel, n_vel, s, i);
+    if (!hi.ok) return;
+    const int64_t c0 = cl_cell(hi.x, inv_c), c1 = cl_cell(hi.y, inv_c);
+    const int64_t c2 = cl_cell(hi.u, inv_c), c3 = cl_cell(hi.v, inv_c);
+    for (int o = 0; o < 81; ++o) {
+        const int d0 = o % 3 - 1, d1 = (o / 3) % 3 - 1, d2c = (o / 9) % 3 - 1, d3 = o / 27 - 1;
+        const uint64_t key = cl_cell_key(c0 + d0, c1 + d1, c2 + d2c, c3 + d3);
+        uint64_t slot = key & mask;
+        for (;;) {
+            const uint64_t k = table_key[slot];
+            if (k == kEmptyCell) break;
+            if (k == key) {
+                for (int j = table_head[slot]; j >= 0; j = next[j]) {
+                    if (j <= i) continue;
+                    const ClHit hj = cl_hit(hits, vel, n_vel, s, j);
+                    const double dx = hi.x - hj.x, dy = hi.y - hj.y, du = hi.u - hj.u,
+                                 dv = hi.v - hj.v;
+                    const double dd = ((dx * dx + dy * dy) + du * du) + dv * dv;
+                    if (dd <= eps2) cl_unite(parent, i, j);
+                }
+                break;
+            }
+            slot = (slot + 1) & mask;
+        }
     }
 }
 
@@ -348,19 +366,68 @@ __global__ void cl_out_kernel(const int32_t *root, const int32_t *rep_of_root, i
 size_t r256(size_t n) { return (n + 255) & ~static_cast<size_t>(255); }
 
 struct ClusterLayout {
-    size_t parent, best_nu, best_key, rep_of_root, vel, total;
+    size_t parent, best_nu, best_key, rep_of_root, vel, next, table_key, table_head, total;
+    uint64_t slots;   // hash-table slots: a power of two >= 2 * n_hits
 };
 
 ClusterLayout cluster_layout(int64_t n_hits, int64_t n_vel) {
     ClusterLayout l{};
     const size_t n = static_cast<size_t>(n_hits);
+    l.slots = 64;
+    while (l.slots < 2 * static_cast<uint64_t>(n)) l.slots <<= 1;
     l.parent = 0;
     l.best_nu = l.parent + r256(n * sizeof(int32_t));
     l.best_key = l.best_nu + r256(n * sizeof(uint32_t));
     l.rep_of_root = l.best_key + r256(n * sizeof(uint64_t));
     l.vel = l.rep_of_root + r256(n * sizeof(int32_t));
-    l.total = l.vel + r256(static_cast<size_t>(n_vel) * 2 * sizeof(double));
+    l.next = l.vel + r256(static_cast<size_t>(n_vel) * 2 * sizeof(double));
+    l.table_key = l.next + r256(n * sizeof(int32_t));
+    l.table_head = l.table_key + r256(l.slots * sizeof(uint64_t));
+    l.total = l.table_head + r256(l.slots * sizeof(int32_t));
     return l;
+}
+
+template <bool MB>
+kb_status launch_threshold(const float *psi_phi, int64_t n_img, int64_t h, int64_t w,
+                           int64_t n_vel, float nu_min, kb_hit *hits, int64_t max_hits,
+                           uint64_t *n_hits, void *workspace, int row_lo, int row_hi,
+                           hipStream_t s) {
+    char *ws = static_cast<char *>(workspace);
+    const WorkspaceLayout lay = workspace_layout(n_img, h, w, n_vel);
+    const int nseg = (int)((w + 63) / 64);
+    const int64_t ntiles = (int64_t)nseg * h;
+    const int grid = KBMI_TH_PERSIST ? threshold_grid<MB>() : 0;
+    const int per_xcd = grid / 8;
+    const GatherEntry *disp = reinterpret_cast<const GatherEntry *>(ws + lay.table);
+    const int32_t *order = reinterpret_cast<const int32_t *>(ws + lay.order);
+    if (grid >= 8 && grid % 8 == 0 && per_xcd % KBMI_PERSIST_BS == 0 &&
+        ntiles >= 4 * (int64_t)grid) {
+        PersistMap pm;
+        pm.nseg = nseg;
+        pm.h = (int)h;
+        pm.bs = KBMI_PERSIST_BS;
+        pm.brows = per_xcd / KBMI_PERSIST_BS;
+        pm.nbc = (nseg + pm.bs - 1) / pm.bs;
+        pm.nbr = ((int)h + pm.brows - 1) / pm.brows;
+        pm.generations = (pm.nbc + 7) / 8 * pm.nbr;
+        pm.spin = KBMI_PERSIST_SPIN;
+        uint32_t *sync = reinterpret_cast<uint32_t *>(ws + lay.sync);
+        hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, sync, 8);
+        kb_status st = launch_status("zero_words_kernel");
+        if (st != KB_OK) return st;
+        hipLaunchKernelGGL(search_threshold_persistent_kernel<MB>, dim3((unsigned)grid), dim3(64),
+                           0, s, reinterpret_cast<const float2 *>(psi_phi), (int)n_img, (int)h,
+                           (int)w, disp, (int)table_stride(n_img), order, (int)n_vel, pm, nu_min,
+                           hits, (uint64_t)max_hits,
+                           reinterpret_cast<unsigned long long *>(n_hits), sync, row_lo, row_hi);
+        return launch_status("search_threshold_persistent_kernel");
+    }
+    hipLaunchKernelGGL(search_threshold_kernel<MB>, dim3((unsigned)ntiles), dim3(64), 0, s,
+                       reinterpret_cast<const float2 *>(psi_phi), (int)n_img, (int)h, (int)w,
+                       disp, (int)table_stride(n_img), order, (int)n_vel, nseg, (int)ntiles,
+                       nu_min, hits, (uint64_t)max_hits,
+                       reinterpret_cast<unsigned long long *>(n_hits), row_lo, row_hi);
+    return launch_status("search_threshold_kernel");
 }
 
 }  // namespace
@@ -395,47 +462,21 @@ kb_status kb_search_threshold(const float *psi_phi, int64_t n_img, int64_t h, in
     if (workspace_bytes < lay.total)
         return fail(KB_ENOMEM, "workspace needs %zu bytes (got %zu)", lay.total, workspace_bytes);
     hipStream_t s = (hipStream_t)stream;
-    st = upload_table(t, n_img, vel, n_vel, h, w, 8, workspace, s);
+    int32_t dy_range[2] = {0, 0};
+    st = upload_table(t, n_img, vel, n_vel, h, w, 8, workspace, s, true, dy_range);
     if (st != KB_OK) return st;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s,
                        reinterpret_cast<unsigned long long *>(n_hits));
     st = launch_status("zero_u64_kernel");
     if (st != KB_OK) return st;
-    char *ws = static_cast<char *>(workspace);
-    const int nseg = (int)((w + 63) / 64);
-    const int64_t ntiles = (int64_t)nseg * h;
-    const int grid = KBMI_TH_PERSIST ? threshold_grid() : 0;
-    const int per_xcd = grid / 8;
-    if (grid >= 8 && grid % 8 == 0 && per_xcd % KBMI_PERSIST_BS == 0 && ntiles >= 4 * (int64_t)grid) {
-        PersistMap pm;
-        pm.nseg = nseg;
-        pm.h = (int)h;
-        pm.bs = KBMI_PERSIST_BS;
-        pm.brows = per_xcd / KBMI_PERSIST_BS;
-        pm.nbc = (nseg + pm.bs - 1) / pm.bs;
-        pm.nbr = ((int)h + pm.brows - 1) / pm.brows;
-        pm.generations = (pm.nbc + 7) / 8 * pm.nbr;
-        pm.spin = KBMI_PERSIST_SPIN;
-        uint32_t *sync = reinterpret_cast<uint32_t *>(ws + lay.sync);
-        hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, sync, 8);
-        st = launch_status("zero_words_kernel");
-        if (st != KB_OK) return st;
-        hipLaunchKernelGGL(search_threshold_persistent_kernel, dim3((unsigned)grid), dim3(64), 0,
-                           s, reinterpret_cast<const float2 *>(psi_phi), (int)n_img, (int)h,
-                           (int)w, reinterpret_cast<const GatherEntry *>(ws + lay.table),
-                           (int)table_stride(n_img),
-                           reinterpret_cast<const int32_t *>(ws + lay.order), (int)n_vel, pm,
-                           nu_min, hits, (uint64_t)max_hits,
-                           reinterpret_cast<unsigned long long *>(n_hits), sync);
-        return launch_status("search_threshold_persistent_kernel");
-    }
-    hipLaunchKernelGGL(search_threshold_kernel, dim3((unsigned)ntiles), dim3(64), 0, s,
-                       reinterpret_cast<const float2 *>(psi_phi), (int)n_img, (int)h, (int)w,
-                       reinterpret_cast<const GatherEntry *>(ws + lay.table),
-                       (int)table_stride(n_img), reinterpret_cast<const int32_t *>(ws + lay.order),
-                       (int)n_vel, nseg, (int)ntiles, nu_min, hits, (uint64_t)max_hits,
-                       reinterpret_cast<unsigned long long *>(n_hits));
-    return launch_status("search_threshold_kernel");
+    // Start rows whose displaced rows are all inside the frame.
+    const int row_lo = (int)std::min<int64_t>(h, -(int64_t)dy_range[0]);
+    const int row_hi = (int)std::max<int64_t>(0, h - (int64_t)dy_range[1]);
+    return n_img > TH_NB
+               ? launch_threshold<true>(psi_phi, n_img, h, w, n_vel, nu_min, hits, max_hits,
+                                        n_hits, workspace, row_lo, row_hi, s)
+               : launch_threshold<false>(psi_phi, n_img, h, w, n_vel, nu_min, hits, max_hits,
+                                         n_hits, workspace, row_lo, row_hi, s);
 }
 
 size_t kb_cluster_workspace_bytes(int64_t n_hits, int64_t n_vel) {
@@ -453,8 +494,8 @@ kb_status kb_cluster_hits(const kb_hit *hits, int64_t n_hits, const double *vel,
         return fail(KB_EINVAL, "hits, velocities, rep and workspace must be non-null");
     if (n_vel < 1 || n_vel > 65535)
         return fail(KB_EINVAL, "n_vel must be in [1, 65535] (got %lld)", (long long)n_vel);
-    if (n_hits > (int64_t)CL_TILE * 65535)
-        return fail(KB_EUNSUPPORTED, "at most %d hits per call", CL_TILE * 65535);
+    if (n_hits > (int64_t(1) << 30))
+        return fail(KB_EUNSUPPORTED, "at most 2^30 hits per call");
     if (!(std::isfinite(s) && s >= 0.0)) return fail(KB_EINVAL, "s must be finite and >= 0");
     if (!(std::isfinite(eps) && eps >= 0.0)) return fail(KB_EINVAL, "eps must be finite and >= 0");
     for (int64_t j = 0; j < 2 * n_vel; ++j)
@@ -478,10 +519,24 @@ kb_status kb_cluster_hits(const kb_hit *hits, int64_t n_hits, const double *vel,
     const dim3 b1((unsigned)((n + 255) / 256)), t1(256);
     hipLaunchKernelGGL(cl_init_kernel, b1, t1, 0, st_, parent, best_nu, best_key, rep_of_root, n);
     if ((st = launch_status("cl_init_kernel")) != KB_OK) return st;
-    const unsigned tiles = (unsigned)((n + CL_TILE - 1) / CL_TILE);
-    hipLaunchKernelGGL(cl_pairs_kernel, dim3(tiles, tiles), dim3(CL_TILE), 0, st_, hits, n, dvel,
-                       (int)n_vel, s, eps * eps, parent);
-    if ((st = launch_status("cl_pairs_kernel")) != KB_OK) return st;
+    uint64_t *table_key = reinterpret_cast<uint64_t *>(ws + lay.table_key);
+    int32_t *table_head = reinterpret_cast<int32_t *>(ws + lay.table_head);
+    int32_t *next = reinterpret_cast<int32_t *>(ws + lay.next);
+    const uint64_t mask = lay.slots - 1;
+    // Cells slightly wider than eps, so that rounding in coordinate / side
+    // never separates two hits at distance eps by two cells (eps = 0: cells
+    // of side 1; only identical hits join).
+    const double side = eps > 0.0 ? eps * (1.0 + 0x1p-20) : 1.0;
+    const double inv_c = 1.0 / side;
+    hipLaunchKernelGGL(cl_table_init_kernel, dim3(2048), dim3(256), 0, st_, table_key, table_head,
+                       (int64_t)lay.slots);
+    if ((st = launch_status("cl_table_init_kernel")) != KB_OK) return st;
+    hipLaunchKernelGGL(cl_insert_kernel, b1, dim3(CL_THREADS), 0, st_, hits, n, dvel, (int)n_vel,
+                       s, inv_c, table_key, table_head, mask, next);
+    if ((st = launch_status("cl_insert_kernel")) != KB_OK) return st;
+    hipLaunchKernelGGL(cl_grid_pairs_kernel, b1, dim3(CL_THREADS), 0, st_, hits, n, dvel,
+                       (int)n_vel, s, inv_c, eps * eps, table_key, table_head, mask, next, parent);
+    if ((st = launch_status("cl_grid_pairs_kernel")) != KB_OK) return st;
     hipLaunchKernelGGL(cl_flatten_kernel, b1, t1, 0, st_, parent, n);
     if ((st = launch_status("cl_flatten_kernel")) != KB_OK) return st;
     hipLaunchKernelGGL(cl_best_nu_kernel, b1, t1, 0, st_, hits, parent, best_nu, n);

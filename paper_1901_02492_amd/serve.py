@@ -229,7 +229,14 @@ def footprint_bytes(n_img, h, w, n_vel, k, k_cand, lp=None) -> int:
     planes = n_img * px * (8 + (4 if lp else 0))
     cand = px * k_cand * 14
     out = 0 if in_place(k, k_cand, lp) else px * k * 14
-    ws = (((n_img + 15) // 16) * 16 * n_vel * 8) + 4 * n_vel + 4096
+    # The request's kb_search / kb_topk workspace and its share of a batch's
+    # workspace: a 16-byte gather-table entry per (velocity, image slot), the
+    # visiting order, the 16-bit scales and counters, each 256-byte rounded,
+    # plus the batch's job descriptor.
+    r256 = lambda b: (b + 255) // 256 * 256
+    stride = (n_img + 15) // 16 * 16
+    one = r256(stride * n_vel * 16) + r256(4 * n_vel) + r256(stride * 8) + 256
+    ws = 2 * one + 4096
     return inputs + planes + cand + out + ws
 
 

@@ -259,7 +259,7 @@ def test_threshold_and_cluster_argument_checks():
     assert cl(s=float("nan")) == lib.KB_EINVAL
     assert cl(rep=None) == lib.KB_EINVAL
     assert cl(wsb=16) == lib.KB_ENOMEM
-    assert cl(n=256 * 65535 + 1) == lib.KB_EUNSUPPORTED
+    assert cl(n=(1 << 30) + 1) == lib.KB_EUNSUPPORTED
     assert L.kb_cluster_workspace_bytes(1000, 4) >= 1000 * 20
     assert lib.HIT_DTYPE.itemsize == 24
 
