@@ -29,7 +29,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["threshold_hits", "features", "pairs_within", "components", "representatives",
-           "cluster"]
+           "cluster", "pairs_within_sparse", "components_sparse", "cluster_sparse"]
 
 
 def threshold_hits(all_nu, m):
@@ -97,4 +97,51 @@ def cluster(xs, ys, js, nu32, vel, s, eps):
     representative index of every hit and the component labels."""
     f = features(xs, ys, js, vel, s)
     labels = components(pairs_within(f, eps))
+    return representatives(labels, nu32, xs, ys, js), labels
+
+
+def pairs_within_sparse(f, eps):
+    """The pairs (a, b), a < b, with d2 <= eps^2 (step 2's test, in its order),
+    for many hits: candidate pairs from a k-d tree query at a radius slightly
+    above eps (a library routine), each then decided by the exact test."""
+    from scipy.spatial import cKDTree
+    f = np.asarray(f, dtype=np.float64)
+    ok = np.all(np.isfinite(f), axis=1)
+    idx = np.nonzero(ok)[0]
+    if idx.size < 2:
+        return np.zeros((0, 2), dtype=np.int64)
+    tree = cKDTree(f[idx])
+    cand = tree.query_pairs(r=float(eps) * (1.0 + 1e-9) + 1e-300, output_type="ndarray")
+    if cand.size == 0:
+        return np.zeros((0, 2), dtype=np.int64)
+    a, b = idx[cand[:, 0]], idx[cand[:, 1]]
+    d = f[a] - f[b]
+    d2 = ((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]) + d[:, 3] * d[:, 3]
+    keep = d2 <= float(eps) * float(eps)
+    lo, hi = np.minimum(a, b)[keep], np.maximum(a, b)[keep]
+    return np.stack([lo, hi], axis=1)
+
+
+def components_sparse(n, pairs):
+    """Connected components of n nodes joined by `pairs` (a library routine);
+    each node's label is the smallest node index of its component."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    g = coo_matrix((np.ones(pairs.shape[0]), (pairs[:, 0], pairs[:, 1])), shape=(n, n))
+    _, lab = connected_components(g, directed=False)
+    smallest = np.full(lab.max() + 1 if n else 0, n, dtype=np.int64)
+    np.minimum.at(smallest, lab, np.arange(n))
+    return smallest[lab]
+
+
+def cluster_sparse(xs, ys, js, nu32, vel, s, eps):
+    """cluster() for many hits: the same groups and representatives, with the
+    pairs found by pairs_within_sparse instead of the dense n x n test."""
+    js = np.asarray(js, dtype=np.int64)
+    nv = np.asarray(vel).reshape(-1, 2).shape[0]
+    bad = (js < 0) | (js >= nv)
+    f = features(xs, ys, np.where(bad, 0, js), vel, s)
+    f[bad] = np.nan                             # outside the grid: a group of its own
+    labels = components_sparse(f.shape[0], pairs_within_sparse(f, eps))
     return representatives(labels, nu32, xs, ys, js), labels

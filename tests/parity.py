@@ -134,6 +134,15 @@ def oracle_full_as_pixels(ref):
             ref["vel"].reshape(P, -1))
 
 
+def lp_kcand(lp, k, n_vel):
+    """Candidates a 16-bit search keeps before the FP32 re-score selects k:
+    k for FP16 (its top-k recall meets 0.999 at K' = K), about 1.25 k for
+    BF16 (8 significant bits: at K' = K its recall falls just short)."""
+    if lp == "bf16":
+        return int(min(n_vel, 64, k + max(2, k // 4)))
+    return int(k)
+
+
 # Unit roundoff of the 16-bit formats (round to nearest even).
 LP_U = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 

@@ -520,9 +520,11 @@ def test_lp_search_rescored(torch_dev, lp, which):
         assert np.all(in_ref | (nu_o >= (nu_k - band)[:, None]))
         in_gpu = (top[:, :, None] == j_g[:, None, :]).any(-1)
         assert np.all(in_gpu | (all_nu[top, pidx] <= (nu_k + band)[:, None]))
-    recall = in_gpu.mean()
-    _say(f"{lp} {which}: recall {recall:.5f}")
-    assert recall >= 0.99
+        # tie-tolerant recall: a kept entry counts when the oracle ranks it in
+        # its top k or within the nu tolerance of its k-th value
+        recall = (in_ref | (nu_o >= (nu_k - parity.tol_nu(nu_k))[:, None])).mean()
+    _say(f"{lp} {which}: recall {recall:.5f} (exact membership {in_gpu.mean():.5f})")
+    assert recall >= 0.999
 
 
 @pytest.mark.parametrize("lp", [None, "f16", "bf16"])

@@ -1,0 +1,194 @@
+"""Every search path a benchmark runs, compared with the FP64 oracle through the
+C ABI: the float32 strip order, the float32 persistent order, the 16-bit
+(FP16, BF16) search before and after its FP32 re-score, and the batched
+(serving) kernel, each at N <= 8, 8 < N <= 16 and N > 16 images (one, two or
+more load batches per velocity)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_02492_amd import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1901_02492_amd import lib
+    lib.load()
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _stack(seed, n, h, w, n_vel, k, vx=None, vy=None):
+    """A random stack; with vx, vy ranges the velocities are a vx x vy grid
+    instead (slow enough in y that most start rows keep every displaced row in
+    the frame, so the interior-row path of the search runs beside the edge
+    path)."""
+    s = synth.random_stack(seed, n=n, h=h, w=w, n_vel=n_vel, k=k, psf_size=5,
+                           vmax=max(h, w) * 0.15, tmax=4.0)
+    if vx is not None:
+        nx = n_vel // 8
+        vel = synth.velocity_grid_xy(np.linspace(*vx, nx), np.linspace(*vy, 8))
+        s = dataclasses.replace(s, vel=vel)
+    return s
+
+
+# The stacks of the matrix, shared by the paths (the oracle runs once each).
+# name: (seed, n, h, w, n_vel, k, vx, vy)
+STACKS = {
+    "n6_strip": (101, 6, 40, 200, 24, 6, None, None),
+    "n12_strip": (102, 12, 33, 150, 20, 5, None, None),
+    "n25_strip": (103, 25, 20, 130, 16, 4, None, None),
+    # 16-bit planes take the super-strip order when the width is a multiple of 1024
+    "n6_super": (104, 6, 24, 1024, 16, 5, None, None),
+    # >= 8192 one-wave tiles at K' = 50: the float32 persistent order
+    "n12_persist": (105, 12, 130, 4100, 64, 50, (-80.0, 300.0), (-8.0, 8.0)),
+    "n25_persist": (106, 25, 128, 4160, 80, 50, (-60.0, 400.0), (-6.0, 6.0)),
+    "n1_strip": (107, 1, 17, 90, 10, 4, None, None),
+    "n9_row": (108, 9, 1, 200, 12, 4, None, None),
+}
+
+_cache = {}
+
+
+def _reference(name):
+    if name not in _cache:
+        seed, n, h, w, nv, k, vx, vy = STACKS[name]
+        s = _stack(seed, n, h, w, nv, k, vx, vy)
+        ref = oracle.search(s.img, s.var, s.mask, s.t, s.psf, s.vel, k)
+        # sum of |psi| along every trajectory: the scale of the 16-bit
+        # rounding error of Psi
+        disp = oracle.displacements(s.t, s.vel)
+        ok = oracle.validity(s.img, s.var, s.mask)
+        S_abs, _, _ = oracle.trajectory_sums(np.abs(ref["psi"]), ref["phi"], ok, disp)
+        ref["all_Sabs"] = S_abs
+        _cache[name] = (s, ref)
+    return _cache[name]
+
+
+def _device(torch, s):
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (s.img, s.var, s.mask))
+
+
+def _check_plain(res, s, ref, k):
+    H, W = s.img.shape[1:]
+    gpu = [r.reshape(H * W, k) for r in res]
+    return parity.check_topk(gpu, *parity.oracle_full_as_pixels(ref), k)
+
+
+MATRIX_F32 = ["n6_strip", "n12_strip", "n25_strip", "n12_persist", "n25_persist"]
+
+
+@pytest.mark.parametrize("name", MATRIX_F32)
+def test_f32_paths(torch_dev, name):
+    """Float32 planes, strip order (small frames) and persistent order (frames
+    of >= 8192 tiles), one to two load batches per velocity."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    s, ref = _reference(name)
+    k = s.k
+    _say(f"f32 {name}: N={s.img.shape[0]} {s.img.shape[1]}x{s.img.shape[2]} "
+         f"V={s.vel.shape[0]} k={k}")
+    img, var, mask = _device(torch, s)
+    planes, res = lib.run_search(img, var, mask, s.t, s.psf, s.vel, k)
+    torch.cuda.synchronize()
+    parity.check_planes(planes.cpu().numpy(), ref["psi"], ref["phi"],
+                        oracle.validity(s.img, s.var, s.mask))
+    _check_plain(parity.to_numpy(res), s, ref, k)
+
+
+MATRIX_LP = ["n6_super", "n12_strip", "n25_strip", "n25_persist"]
+
+
+@pytest.mark.parametrize("name", MATRIX_LP)
+@pytest.mark.parametrize("lp", ["f16", "bf16"])
+def test_lp_paths(torch_dev, name, lp):
+    """16-bit planes (per-image scales, every load batch with its own): the
+    candidates before the re-score against the oracle within the propagated
+    16-bit bound, then the FP32 re-score of K' candidates to the final K
+    against the oracle, bitwise equal to the plain path, with recall >= 0.999
+    (K' from parity.lp_kcand).  BF16 at K' = K is measured as well, and must
+    keep 0.995."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    s, ref = _reference(name)
+    n, h, w = s.img.shape
+    k = s.k
+    nv = s.vel.shape[0]
+    img, var, mask = _device(torch, s)
+    planes, src, sc = lib.make_psi_phi(img, var, mask, s.psf, lp=lp)
+    plain = parity.to_numpy(lib.topk(lib.search(planes, s.t, s.vel, k), k, n))
+    ws = lib.alloc_workspace(n, h, w, nv, img.device)
+    kcs = [parity.lp_kcand(lp, k, nv)] + ([k] if lp == "bf16" and k < nv else [])
+    for kc in dict.fromkeys(kcs):
+        _say(f"{lp} {name}: N={n} {h}x{w} V={nv} k={k} k_cand={kc}")
+        cand = lib.search(src, s.t, s.vel, kc, workspace=ws, lp_scale=sc)
+        torch.cuda.synchronize()
+        worst = parity.check_lp_candidates(parity.to_numpy(cand), s, ref, lp, kc)
+        res = lib.topk(cand, k, n, rescore=(planes, s.t, s.vel, ws))
+        torch.cuda.synchronize()
+        recall = parity.check_rescored(parity.to_numpy(res), plain, s, ref, k)
+        _say(f"{lp} {name} K'={kc}: 16-bit nu error max {worst:.2e} (R15 units), "
+             f"recall {recall:.6f}")
+        assert recall >= (0.999 if kc == kcs[0] else 0.995)
+
+
+@pytest.mark.parametrize("lp", [None, "f16", "bf16"])
+def test_batched_paths(torch_dev, lp):
+    """kb_search_batch over stacks of 1, 6, 9, 12 and 25 images (one of them a
+    single row) against the oracle: plain lists directly, 16-bit lists before
+    and after the FP32 re-score."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    names = ["n6_strip", "n12_strip", "n25_strip", "n1_strip", "n9_row"]
+    k = min(STACKS[nm][5] for nm in names)      # one k_cand per batch
+    kc = k if lp is None else parity.lp_kcand(lp, k, min(STACKS[nm][4] for nm in names))
+    jobs, refs = [], []
+    for name in names:
+        s, ref = _reference(name)
+        img, var, mask = _device(torch, s)
+        if lp is None:
+            planes = src = lib.make_psi_phi(img, var, mask, s.psf)
+            sc = None
+        else:
+            planes, src, sc = lib.make_psi_phi(img, var, mask, s.psf, lp=lp)
+        h, w = s.img.shape[1:]
+        out = lib.alloc_candidates(h, w, kc, img.device)
+        jobs.append(dict(planes=src, t=s.t, vel=s.vel, out=out, lp_scale=sc))
+        refs.append((name, s, ref, planes))
+    _say(f"batch {lp}: {names} k_cand={kc}")
+    lib.search_batch(jobs, kc)
+    torch.cuda.synchronize()
+    for jb, (name, s, ref, planes) in zip(jobs, refs):
+        got = parity.to_numpy(jb["out"])
+        n = s.img.shape[0]
+        ref_k = oracle.search(s.img, s.var, s.mask, s.t, s.psf, s.vel, kc)
+        ref_k["all_Sabs"] = ref["all_Sabs"]
+        ref_k["psi"], ref_k["phi"] = ref["psi"], ref["phi"]
+        if lp is None:
+            _check_plain(got, s, ref_k, kc)
+            continue
+        parity.check_lp_candidates(got, s, ref_k, lp, kc)
+        h, w = s.img.shape[1:]
+        ws = lib.alloc_workspace(n, h, w, s.vel.shape[0], planes.device)
+        res = lib.topk(jb["out"], k, n, rescore=(planes, s.t, s.vel, ws))
+        plain = lib.topk(lib.search(planes, s.t, s.vel, k), k, n)
+        torch.cuda.synchronize()
+        ref_top = oracle.search(s.img, s.var, s.mask, s.t, s.psf, s.vel, k)
+        recall = parity.check_rescored(parity.to_numpy(res), parity.to_numpy(plain), s, ref_top,
+                                       k)
+        _say(f"batch {lp} {name}: recall {recall:.6f}")
+        assert recall >= 0.999

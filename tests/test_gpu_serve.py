@@ -1,10 +1,15 @@
-"""Served requests return exactly what the same requests return alone.
+"""Served requests return exactly what the same requests return alone, and
+what the FP64 oracle returns for them.
 
 The server batches whatever is prepared into one kb_search_batch launch and
 overlaps requests on two streams; the search arithmetic per tile is the
 single-stack one and sums run in image order, so results must be bitwise
 equal to a solo run (FP32 path, and the 16-bit search with FP32 re-score)."""
+import numpy as np
 import pytest
+
+import oracle
+from tests import parity
 
 torch = pytest.importorskip("torch")
 
@@ -61,3 +66,31 @@ def test_served_equals_solo(lp):
         torch.cuda.synchronize()
         for name, a, b in zip(("nu", "alpha", "vel", "nobs"), d.result, solo):
             assert torch.equal(a, b), f"request {r.rid} {name} differs from its solo run"
+        _check_oracle(r, d.result, lp)
+
+
+def _check_oracle(req, result, lp):
+    """A served request's top-k against the FP64 oracle on the same inputs
+    (copied back from the device): the plain path to the FP32 tolerances with
+    near-ties allowed at the cut; after a 16-bit search and the FP32 re-score,
+    every kept value to the FP32 tolerances and a tie-tolerant recall of at
+    least 0.999."""
+    img, var, mask = (x.cpu().numpy() for x in req.make())
+    n, h, w = img.shape
+    ref = oracle.search(img, var, mask, req.t, req.psf, req.vel, req.k)
+    got = [x.cpu().numpy().reshape(h * w, req.k) for x in result]
+    full = parity.oracle_full_as_pixels(ref)
+    if lp is None:
+        parity.check_topk(got, *full, req.k)
+        return
+    all_nu, all_al, all_no, all_phi, top = full
+    nu_g, al_g, j_g, n_g = got
+    pidx = np.arange(h * w)[:, None]
+    nu_o = all_nu[j_g, pidx]
+    fin = np.isfinite(nu_o)
+    assert np.array_equal(n_g.astype(np.int64), all_no[j_g, pidx])
+    assert np.all(np.abs(nu_g - nu_o)[fin] <= parity.tol_nu(nu_o)[fin])
+    kth = all_nu[top[:, req.k - 1], np.arange(h * w)]
+    with np.errstate(invalid="ignore"):
+        ok = parity.member(j_g, top, all_nu.shape[0]) | (nu_o >= (kth - parity.tol_nu(kth))[:, None])
+    assert ok.mean() >= 0.999, f"request {req.rid}: recall {ok.mean():.5f}"

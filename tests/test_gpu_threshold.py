@@ -172,6 +172,36 @@ def test_cluster_random_points_with_long_chains(torch_dev):
     np.testing.assert_array_equal(rep, rep_o)     # same order: same indices
 
 
+@pytest.mark.parametrize("n,eps,s", [(200_000, 4.0, 2.24), (300_000, 2.0, 0.5)])
+def test_cluster_many_hits_against_sparse_oracle(torch_dev, n, eps, s):
+    """Hundreds of thousands of hits (survey-sized frame and velocity grid,
+    clumps of nearby trajectories around random centres, ties in nu, a few
+    indices outside the grid) against the oracle's k-d tree clustering: every
+    hit's representative index is the oracle's."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    rng = np.random.default_rng(67 + n)
+    vel = synth.survey_velocities(25, 24)
+    nc = n // 20
+    cx, cy = rng.integers(0, 4096, nc), rng.integers(0, 4096, nc)
+    cj = rng.integers(0, vel.shape[0], nc)
+    pick = rng.integers(0, nc, n)
+    xs = np.clip(cx[pick] + rng.integers(-6, 7, n), 0, 4095)
+    ys = np.clip(cy[pick] + rng.integers(-6, 7, n), 0, 4095)
+    js = np.clip(cj[pick] + rng.integers(-2, 3, n), 0, vel.shape[0] - 1)
+    key = np.unique(np.stack([ys, xs, js], 1), axis=0)           # distinct trajectories
+    key = key[rng.permutation(key.shape[0])]
+    ys, xs, js = key[:, 0], key[:, 1], key[:, 2].copy()
+    js[:7] = [-1, vel.shape[0], 70000, -5, vel.shape[0] + 3, -1, 99999]
+    nu32 = rng.choice(np.array([10.0, 11.5, 12.0, 20.0], dtype=np.float32), ys.size)
+    rep_o, lab = oc.cluster_sparse(xs, ys, js, nu32, vel, s, eps)
+    _say(f"case cluster many: {ys.size} hits, {len(set(lab.tolist()))} groups, "
+         f"s={s} eps={eps}")
+    d = _upload_hits(torch, _oracle_records(ys, xs, js, nu32))
+    rep = lib.cluster_hits(d, ys.size, vel, s, eps).cpu().numpy()
+    np.testing.assert_array_equal(rep, rep_o)
+
+
 @pytest.mark.slow
 def test_survey_threshold_and_clusters(torch_dev):
     """The survey stack at nu >= 10 (the Sec. 3.2 cut): hits on sampled start

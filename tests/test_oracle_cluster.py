@@ -78,3 +78,34 @@ def test_threshold_hits_are_the_trajectories_at_or_above_m():
     # The source at (20, 30) moving (40, 25) px/d is among them.
     j_true = int(np.nonzero((s.vel[:, 0] == 40.0) & (s.vel[:, 1] == 20.0))[0][0])
     assert any((y, x, j) == (30, 20, j_true) for y, x, j in zip(ys, xs, js))
+
+
+@pytest.mark.parametrize("seed,eps,s", [(0, 2.0, 0.5), (1, 3.0, 1.0), (2, 1.0, 0.0),
+                                        (3, 0.0, 1.0), (4, 4.0, 2.24)])
+def test_sparse_pairs_equal_the_dense_test(seed, eps, s):
+    """The k-d tree candidate pairs with the exact test give the dense test's
+    groups and representatives, on integer positions and a coarse velocity
+    grid where distances of exactly eps are common (they join)."""
+    rng = np.random.default_rng(900 + seed)
+    n = 1500
+    vel = np.stack(np.meshgrid(np.arange(-3.0, 4.0), np.arange(-2.0, 3.0)), -1).reshape(-1, 2)
+    xs = rng.integers(0, 40, n)
+    ys = rng.integers(0, 30, n)
+    js = rng.integers(0, vel.shape[0], n)
+    nu = rng.integers(0, 5, n).astype(np.float32)       # many ties
+    rep_d, lab_d = oc.cluster(xs, ys, js, nu, vel, s, eps)
+    rep_s, lab_s = oc.cluster_sparse(xs, ys, js, nu, vel, s, eps)
+    assert np.array_equal(lab_d, lab_s)
+    assert np.array_equal(rep_d, rep_s)
+    d = oc.pairs_within(oc.features(xs, ys, js, vel, s), eps)
+    p = oc.pairs_within_sparse(oc.features(xs, ys, js, vel, s), eps)
+    assert p.shape[0] == int(np.triu(d, 1).sum())
+
+
+def test_sparse_clustering_puts_out_of_grid_hits_alone():
+    vel = np.array([[0.0, 0.0], [1.0, 0.0]])
+    xs, ys = np.array([5, 5, 5]), np.array([7, 7, 8])
+    js = np.array([0, 7, 1])
+    nu = np.array([1.0, 9.0, 2.0], np.float32)
+    rep, lab = oc.cluster_sparse(xs, ys, js, nu, vel, 1.0, 2.0)
+    assert lab.tolist() == [0, 1, 0] and rep.tolist() == [2, 1, 2]
