@@ -7,9 +7,12 @@ final per-pixel top-k (kb_topk).  Default workload: 15 images of 4096 x 4096
 over 3 nights, 600 velocities, K = 50 (about 1e10 trajectories).
 
 Prints one JSON line with trajectory-image evaluations per second
-(N * H * W * V per step / step time), the search kernel's fraction of the HBM
-gather roofline (8 bytes of psi/phi per evaluation against 8 TB/s) and the
-FP64 oracle's throughput on the host cores for context.
+(N * H * W * V per step / step time); the search kernel's roofline: its
+algorithmic bytes (8 bytes of psi/phi per evaluation) per second against the
+measured peak of its own load pattern from L2, which serves most of its
+gathers, with its counted HBM traffic against 8 TB/s beside it; the FP64 C
+oracle's throughput on the host cores on a block of start rows; and the
+top-K recall of the GPU against that oracle on those rows.
 """
 from __future__ import annotations
 
@@ -73,49 +76,112 @@ def make_stack(workload):
     raise SystemExit(f"unknown workload {workload}")
 
 
-# --- CPU baseline: the FP64 oracle on crops of the same stack ---------------
-_CPU_STACK = None
+# --- CPU baseline: the FP64 C oracle on a block of start rows ----------------
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
-_CPU_BRIGHT = None
-
-
-def _oracle_crop(arg):
+def cpu_baseline(s, bright=None, extra=8):
+    """The C oracle (oracle/kb_oracle.c) on a block of full-width start rows in
+    the middle of the frame, on the host's worker processes: its planes for
+    every row those trajectories visit, then its best K + extra trajectories
+    of every start pixel of the block.  Returns (the baseline object, the
+    oracle's arrays and row range, kept to compare with the GPU)."""
     import oracle
-    y0, x0, c = arg
-    s = _CPU_STACK
-    sl = (slice(None), slice(y0, y0 + c), slice(x0, x0 + c))
-    t0 = time.perf_counter()
-    mask = s.mask[sl]
-    if _CPU_BRIGHT is not None:
-        mask = oracle.bright_mask(s.img[sl], mask, _CPU_BRIGHT)
-    oracle.search(s.img[sl], s.var[sl], mask, s.t, s.psf, s.vel, s.k)
-    return time.perf_counter() - t0
-
-
-def cpu_baseline(s, crop=224, bright=None):
-    """Run the oracle on one crop per worker process (all images, all
-    velocities; the bright-pixel mask first when a level is given)."""
-    global _CPU_STACK, _CPU_BRIGHT
-    _CPU_STACK = s
-    _CPU_BRIGHT = bright
+    from oracle import bands
     n, h, w = s.img.shape
-    workers = max(1, min(16, os.cpu_count() or 1))
-    c = min(crop, h, w)
-    rng = np.random.default_rng(0)
-    args = [(int(rng.integers(0, h - c + 1)), int(rng.integers(0, w - c + 1)), c)
-            for _ in range(workers)]
-    ctx = mp.get_context("fork")
+    nv = s.vel.shape[0]
+    rows = int(min(h, max(16, 256 * 600 // nv)))
+    r0 = max(0, h // 2 - rows // 2)
+    r1 = r0 + rows
+    workers = max(1, min(15, (os.cpu_count() or 2) - 1))
+    mask = s.mask if bright is None else oracle.bright_mask(s.img, s.mask, bright)
     t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
-        per = pool.map(_oracle_crop, args)
+    arrays, timing = bands.run_bands(s.img, s.var, mask, s.psf, s.t, s.vel, s.k + extra, r0, r1,
+                                     band_rows=16, workers=workers)
     wall = time.perf_counter() - t0
-    tie = workers * n * c * c * s.vel.shape[0]
-    return {"value": tie / wall, "unit": "trajectory-image evals/s", "cores": workers,
-            "kind": "oracle",
-            "sample": f"{workers} crops of {c}x{c} start pixels (all {n} images, all "
-                      f"{s.vel.shape[0]} velocities, K={s.k}), one FP64 numpy oracle process "
-                      f"per crop; wall {wall:.1f} s, per-crop {min(per):.1f}-{max(per):.1f} s"}
+    tie = n * rows * w * nv
+    base = {"value": tie / wall, "unit": "trajectory-image evals/s", "cores": workers,
+            "kind": "oracle", "cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+            "sample": f"start rows {r0}-{r1 - 1} ({rows} full-width rows, {rows * w} start "
+                      f"pixels, all {n} images and {nv} velocities: {tie:.3g} TIE); the FP64 C "
+                      f"oracle's planes for the {timing['plane_rows']} rows those trajectories "
+                      f"visit ({timing['planes_s']:.1f} s), then its best K+{extra} of every "
+                      f"start pixel ({timing['search_s']:.1f} s), on {workers} worker "
+                      f"processes; wall {wall:.1f} s"}
+    return base, (arrays, r0, r1)
+
+
+def recall_vs_fp64(oracle_rows, res, k):
+    """The GPU's ranked top-k lists of the oracle's rows against the oracle
+    (tests.parity.check_band: exact indices and n_obs, FP32 tolerances,
+    tie-tolerant set): the fraction of GPU entries that the oracle ranks in
+    its top k or within the nu tolerance of its k-th value."""
+    from tests import parity
+    arrays, r0, r1 = oracle_rows
+    got = [t[r0:r1].cpu().numpy() for t in res]
+    st = parity.check_band(got, arrays, k)
+    return {"value": st["recalled"] / st["entries"], "rows": f"{r0}-{r1 - 1}",
+            "pixels": st["pixels"], "near_tie_pixels": st["near_tie_pixels"],
+            "nu_err_max": st["nu_err"], "alpha_err_max_of_tol": st["alpha_err"],
+            "check": "velocity indices and n_obs exact, nu/alpha within the FP32 tolerances, "
+                     "top-K set equal to the FP64 oracle's up to near-ties"}
+
+
+# --- The gather pattern's measured peak (the roof of the search kernel) ------
+PEAK_ROW_BYTES = 4096 * 8          # one survey row of (psi, phi) pairs
+
+
+def gather_peak(torch, dev, cus, width=8, sweep=False):
+    """Throughput of the search's load pattern (kbp_gather_peak: `width`
+    bytes per lane, one unaligned 64 * width-byte run per wave and load, at
+    random rows) from a 2 MiB region, which every XCD's 4 MB L2 holds, and
+    from a 4 GiB region (HBM), at 2 and 8 (with sweep, also 4) waves per SIMD
+    and 16 or 32 loads in flight per wave.  GB/s of bytes requested, best of
+    two launches each."""
+    import ctypes
+    from paper_1901_02492_amd import build as _build
+    if not os.path.exists(_build.PEAK_LIB):
+        return None
+    L = ctypes.CDLL(_build.PEAK_LIB)
+    f = L.kbp_gather_peak
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    regions = {"l2": 2 << 20, "hbm": 4 << 30}
+    per_simd = (2, 4, 8) if sweep else (2, 8)
+    for name, nbytes in regions.items():
+        rows = nbytes // PEAK_ROW_BYTES
+        region = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        sink = torch.zeros(cus * 4 * 8 * 64, dtype=torch.float32, device=dev)
+        for ws in per_simd:
+            waves = cus * 4 * ws
+            for nb in (16, 32):
+                run = 64 * width
+                iters = max(1, int((40e9 if name == "l2" else 8e9) / (waves * nb * run)))
+                best = None
+                for rep in range(2):
+                    ms = f(region.data_ptr(), rows, PEAK_ROW_BYTES, waves, iters, nb, width,
+                           17 + rep, sink.data_ptr(), stream)
+                    if ms <= 0:
+                        raise RuntimeError(f"kbp_gather_peak failed ({ms})")
+                    best = ms if best is None else min(best, ms)
+                gbs = waves * iters * nb * run / (best * 1e-3) / 1e9
+                out[f"{name}_w{ws}_nb{nb}"] = gbs
+        del region, sink
+    res = {"l2_gbs": max(v for k_, v in out.items() if k_.startswith("l2")),
+           "l2_2wave_gbs": max(v for k_, v in out.items() if k_.startswith("l2_w2_")),
+           "hbm_gather_gbs": max(v for k_, v in out.items() if k_.startswith("hbm")),
+           "all": out}
+    return res
 
 
 def main():
@@ -125,7 +191,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="survey",
                     choices=["survey", "small", "serve", "large", "lcfilter", "hits",
-                             "threshold", "stamps"])
+                             "threshold", "stamps", "cluster"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="f32", choices=["f32", "f16", "bf16"],
                     help="survey/hits: plane format searched (16-bit formats are "
@@ -139,6 +205,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM "
                          "byte counters) and exit")
+    ap.add_argument("--gather-peak", action="store_true",
+                    help="only measure the search's gather pattern from L2 and from HBM "
+                         "(kbp_gather_peak) at 2, 4 and 8 waves per SIMD and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the search runs on a single device "
@@ -156,12 +225,24 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "copies": 2}), flush=True)
         return
 
+    if args.gather_peak:
+        import torch
+        dev = torch.device("cuda:0")
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        for width in (8, 4):
+            pk = gather_peak(torch, dev, cus, width=width, sweep=True)
+            print(json.dumps({"gather_peak_bytes_per_lane": width, "cus": cus, **pk}),
+                  flush=True)
+        return
+
     if args.workload in ("serve", "large"):
         return serve_bench(args)
     if args.workload == "lcfilter":
         return lcfilter_bench(args)
     if args.workload == "threshold":
         return threshold_bench(args)
+    if args.workload == "cluster":
+        return cluster_bench(args)
     if args.workload == "stamps":
         return stamps_bench(args)
 
@@ -175,11 +256,11 @@ def main():
     if args.workload == "hits":
         from paper_1901_02492_amd import synth
         bright = synth.HITS_BRIGHT_SIGMA
-    cpu = None
+    cpu = oracle_rows = None
     if not args.no_cpu_baseline:
-        # Crops small enough that the oracle's [V][crop][crop] arrays stay modest.
-        cpu = cpu_baseline(s, crop=224 if nv <= 2000 else 32, bright=bright)
-        log(f"cpu baseline {cpu['value']:.3e} TIE/s on {cpu['cores']} cores")
+        # Runs before the GPU is touched: its worker processes are forked.
+        cpu, oracle_rows = cpu_baseline(s, bright=bright)
+        log(f"cpu baseline {cpu['value']:.3e} TIE/s on {cpu['cores']} worker processes")
 
     import torch
     from paper_1901_02492_amd import lib
@@ -251,6 +332,35 @@ def main():
     tie = s.tie
     bytes_per_tie = BYTES_PER_TIE_F32 if lp is None else BYTES_PER_TIE_F32 / 2
     achieved = bytes_per_tie * tie / (search_ms * 1e-3) / 1e9
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    peak = gather_peak(torch, dev, cus, width=8 if lp is None else 4)
+    traffic = measured_traffic() if (lp is None and kc == s.k and args.workload == "survey") \
+        else None
+    hbm_gbs = None if traffic is None else traffic / (search_ms * 1e-3) / 1e9
+    if peak is not None:
+        log(f"gather peak {peak['l2_gbs']:.0f} GB/s from L2 (2 waves/SIMD "
+            f"{peak['l2_2wave_gbs']:.0f}), {peak['hbm_gather_gbs']:.0f} GB/s from HBM")
+        roof = {"bound": "l2", "kernel": "search_persistent_kernel" if lp is None
+                else "search_kernel", "achieved": achieved, "peak": peak["l2_gbs"],
+                "unit": "GB/s", "frac": achieved / peak["l2_gbs"], "traffic": traffic,
+                "peak_source": f"measured in this run: kbp_gather_peak, {int(8 * bytes_per_tie)}"
+                               f"-byte-per-lane raw buffer loads (one unaligned "
+                               f"{int(64 * bytes_per_tie)}-byte run per wave and load) at random "
+                               f"rows of a 2 MiB region every XCD's L2 holds, best of 2/8 "
+                               f"waves per SIMD and 16/32 loads in flight",
+                "peak_2wave_per_simd": peak["l2_2wave_gbs"],
+                "frac_of_2wave_peak": achieved / peak["l2_2wave_gbs"],
+                "hbm_gather_peak": peak["hbm_gather_gbs"],
+                "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS,
+                        "frac": None if hbm_gbs is None else hbm_gbs / HBM_PEAK_GBS,
+                        "algorithmic_frac": achieved / HBM_PEAK_GBS}}
+    else:
+        roof = {"bound": "hbm", "kernel": "search_kernel", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic}
+    roof.update({"search_ms": search_ms, "search_ms_median": float(np.median(search_each)),
+                 "search_ms_min": float(np.min(search_each)), "topk_ms": topk_ms,
+                 "bytes_per_tie": bytes_per_tie})
     out = {
         "metric": "trajectory-image evals/s",
         "value": tie / (ms_step * 1e-3),
@@ -272,15 +382,14 @@ def main():
                            + (" (re-score from f32 planes)" if lp is not None else
                               " (in place)" if kc == s.k else ""),
                    "bright_threshold": bright},
-        "roofline": {"bound": "hbm", "kernel": "search_kernel", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if (lp is None and kc == s.k
-                                                       and args.workload == "survey") else None,
-                     "search_ms": search_ms, "search_ms_median": float(np.median(search_each)),
-                     "search_ms_min": float(np.min(search_each)), "topk_ms": topk_ms,
-                     "bytes_per_tie": bytes_per_tie},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if oracle_rows is not None:
+        final = cand if (lp is None and kc == s.k) else res
+        out["recall_vs_fp64"] = recall_vs_fp64(oracle_rows, final, s.k)
+        log(f"recall vs the FP64 oracle on rows {out['recall_vs_fp64']['rows']}: "
+            f"{out['recall_vs_fp64']['value']:.7f}")
     if lp is not None:
         out["precision"] = precision_vs_f32(lib, torch, planes, cand, res, s, kc, ws)
     print(json.dumps(out), flush=True)
@@ -460,6 +569,103 @@ TH_EPS = 4.0              # clustering radius (pixels) over (x, y, s*vx, s*vy)
 TH_MAX_HITS = 1 << 22
 
 
+CL_HITS = 10_000_000      # synthetic hits of the clustering workload
+CL_EPS = 4.0              # px, as in the threshold workload
+
+
+def cluster_hits_synthetic(n, seed=1901_02492 + 5000):
+    """n distinct trajectories (y, x, j) on the survey frame and velocity grid,
+    in clumps of nearby trajectories around random centres (duplicates of a
+    detection), with float32 nu and a few indices outside the grid."""
+    from paper_1901_02492_amd import synth
+    rng = np.random.default_rng(seed)
+    vel = synth.survey_velocities(25, 24)
+    nc = n // 10
+    cx, cy = rng.integers(0, 4096, nc), rng.integers(0, 4096, nc)
+    cj = rng.integers(0, vel.shape[0], nc)
+    m = int(n * 1.1)
+    pick = rng.integers(0, nc, m)
+    xs = np.clip(cx[pick] + rng.integers(-6, 7, m), 0, 4095)
+    ys = np.clip(cy[pick] + rng.integers(-6, 7, m), 0, 4095)
+    js = np.clip(cj[pick] + rng.integers(-2, 3, m), 0, vel.shape[0] - 1)
+    key = np.unique(np.stack([ys, xs, js], 1), axis=0)[:n]
+    key = key[rng.permutation(key.shape[0])]
+    ys, xs, js = key[:, 0], key[:, 1], key[:, 2].copy()
+    js[:5] = [-1, vel.shape[0], 70000, -5, 99999]
+    nu = (10.0 + rng.gamma(2.0, 2.0, ys.size)).astype(np.float32)
+    return ys, xs, js, nu, vel
+
+
+def cluster_bench(args):
+    """kb_cluster_hits on >= 1e7 synthetic hits (the duplicate clustering of
+    Sec. 3.3 at the scale of an unmasked field, Sec. 5.2); the oracle's k-d
+    tree clustering of a 1e6-hit sample is the CPU baseline, and a smaller
+    draw is checked against it on the GPU."""
+    from oracle import cluster as oc
+    span = 2.24
+    t0 = time.perf_counter()
+    ys, xs, js, nu, vel = cluster_hits_synthetic(CL_HITS)
+    n = ys.size
+    log(f"{n} hits generated in {time.perf_counter() - t0:.1f} s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        m = 1_000_000
+        ss, sx, sj, sn, _ = cluster_hits_synthetic(m, seed=7)
+        t0 = time.perf_counter()
+        oc.cluster_sparse(sx, ss, sj, sn, vel, span, CL_EPS)
+        dt = time.perf_counter() - t0
+        cpu = {"value": m / dt, "unit": "hits/s", "cores": 1, "kind": "oracle",
+               "sample": f"{m} hits of the same recipe, oracle.cluster.cluster_sparse (k-d tree "
+                         f"candidate pairs, exact test, connected components) in one process: "
+                         f"{dt:.1f} s"}
+        log(f"cpu baseline {cpu['value']:.3e} hits/s")
+    import torch
+    from paper_1901_02492_amd import lib
+    lib.load()
+    dev = torch.device("cuda:0")
+    rec = np.zeros(n, dtype=lib.HIT_DTYPE)
+    rec["x"], rec["y"], rec["vel"], rec["nu"] = xs, ys, js, nu
+    hits = torch.from_numpy(rec.view(np.int32).reshape(-1, 6).copy()).to(dev)
+    nb = lib.load().kb_cluster_workspace_bytes(n, vel.shape[0])
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        lib.cluster_hits(hits, n, vel, span, CL_EPS, workspace=ws)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        rep = lib.cluster_hits(hits, n, vel, span, CL_EPS, workspace=ws)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ev_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    groups = int(torch.unique(rep).numel())
+    log(f"{args.steps} timed calls: {ms:.2f} ms per call ({ev_ms:.2f} ms on the stream), "
+        f"{groups} groups")
+    # Parity at scale: a 300000-hit draw against the oracle.
+    ps, px, pj, pn, _ = cluster_hits_synthetic(300_000, seed=11)
+    prec = np.zeros(ps.size, dtype=lib.HIT_DTYPE)
+    prec["x"], prec["y"], prec["vel"], prec["nu"] = px, ps, pj, pn
+    ph = torch.from_numpy(prec.view(np.int32).reshape(-1, 6).copy()).to(dev)
+    prep = lib.cluster_hits(ph, ps.size, vel, span, CL_EPS).cpu().numpy()
+    want, _ = oc.cluster_sparse(px, ps, pj, pn, vel, span, CL_EPS)
+    same = bool(np.array_equal(prep, want))
+    log(f"300000-hit draw: representatives equal to the oracle's: {same}")
+    out = {"metric": "hits clustered/s", "value": n / (ev_ms * 1e-3), "unit": "hits/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"duplicate clustering of {n} hits (clumps on a 4096^2 frame, "
+                                  f"600-velocity grid), s = {span} d, eps = {CL_EPS} px",
+                      "hits": n, "groups": groups},
+           "roofline": None, "cpu_baseline": cpu,
+           "parity": {"hits": int(ps.size), "representatives_equal_oracle": same}}
+    print(json.dumps(out), flush=True)
+
+
 def threshold_bench(args):
     """Planes, the threshold search (nu >= 10) and the clustering of its hits
     on the survey stack."""
@@ -469,7 +675,7 @@ def threshold_bench(args):
     log(f"workload {s.name}: generated")
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(s)
+        cpu, _ = cpu_baseline(s)
         cpu["sample"] += "; the oracle scores every trajectory, from which hits are read"
         log(f"cpu baseline {cpu['value']:.3e} TIE/s on {cpu['cores']} cores")
     import torch
@@ -705,6 +911,34 @@ def _quantiles(lat):
             "mean": float(a.mean())}
 
 
+def served_vs_oracle(reqs, results):
+    """Served top-k lists of some requests against the FP64 C oracle on every
+    start pixel of their frames (tests.parity.check_band per row band)."""
+    from oracle import bands
+    from tests import parity
+    out = []
+    for rid, res in results.items():
+        r = reqs[rid]
+        img, var, mask = (x.cpu().numpy() for x in r.make())
+        got = [x.cpu().numpy() for x in res]
+        n, h, w = img.shape
+        t0 = time.perf_counter()
+
+        def check(r0, r1, orc, got=got, k=r.k):
+            return parity.check_band([g[r0:r1] for g in got], orc, k)
+        stats, timing = bands.run_bands(img, var, mask, r.psf, r.t, r.vel, r.k + 8, 0, h,
+                                        band_rows=16, on_band=check)
+        ent = sum(st["entries"] for st in stats)
+        out.append({"rid": rid, "shape": [n, h, w], "n_vel": len(r.vel),
+                    "pixels": sum(st["pixels"] for st in stats),
+                    "recall_vs_fp64": sum(st["recalled"] for st in stats) / ent,
+                    "near_tie_pixels": sum(st["near_tie_pixels"] for st in stats),
+                    "oracle_s": time.perf_counter() - t0})
+        log(f"served request {rid} ({n}x{h}x{w}, {len(r.vel)} velocities) matches the oracle "
+            f"on {out[-1]['pixels']} start pixels")
+    return out
+
+
 def serve_bench(args):
     import threading
     import torch
@@ -781,6 +1015,11 @@ def serve_bench(args):
             solo = _solo(lib, reqs[rid], None)
             same += all(torch.equal(a, b) for a, b in zip(kept[rid], solo))
             del solo
+        # The two smallest sampled requests against the FP64 C oracle on
+        # every start pixel (inputs copied back from the device).
+        oracle_check = served_vs_oracle(
+            reqs, {rid: kept[rid] for rid in sorted(sample, key=lambda q: (
+                np.prod(reqs[q].shape) * len(reqs[q].vel), q))[:2]})
         kept.clear()
         lq = _quantiles([lat[r.rid] for r in reqs])
         out = {
@@ -796,6 +1035,7 @@ def serve_bench(args):
             "server": {"peak_gb": srv.peak_bytes / 1e9, "launches": len(srv.batches),
                        "max_batch": max(srv.batches)},
             "alone_vs_mix": {"checked": len(sample), "bitwise_equal": same},
+            "served_vs_oracle": oracle_check,
         }
         print(json.dumps(out), flush=True)
         return

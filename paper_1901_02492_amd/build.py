@@ -19,6 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libkbmi.so")
+PEAK_LIB = os.path.join(PKG, "libkbmi_peak.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 KM_GROUPS = 8   # list-length groups of the search units (kKmGroups in kbmi_device.h)
@@ -81,5 +82,16 @@ def build_library(verbose: bool = False, out: str = LIB, defines=(), jobs: int =
     return out
 
 
+def build_peak_library(verbose: bool = False, out: str = PEAK_LIB) -> str:
+    """Compile the measurement helper libkbmi_peak.so (the gather-pattern peak
+    the benchmark sets the search kernel against; not part of libkbmi)."""
+    tmp_lib = out + ".tmp"
+    _run([HIPCC, *DEVICE_FLAGS, "-shared", "-o", tmp_lib, os.path.join(CSRC, "kbmi_peak.hip")],
+         verbose)
+    os.replace(tmp_lib, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build_library(verbose="-v" in sys.argv))
+    print(build_peak_library(verbose="-v" in sys.argv))

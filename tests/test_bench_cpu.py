@@ -79,3 +79,24 @@ def test_errors_before_rescore_in_tolerance_units():
     assert out["nu_err_before_rescore"]["max"] == pytest.approx(want, rel=1e-4)
     assert out["nu_err_before_rescore"]["n"] == (H // 2) * W * KC
     assert out["alpha_err_before_rescore"]["max"] == 0.0
+
+
+def test_cpu_baseline_and_recall_on_a_small_stack():
+    """bench.cpu_baseline runs the C oracle on a block of start rows (the TIE
+    it credits are the rows it computes) and recall_vs_fp64 checks lists
+    against it: the oracle's own top-k in float32 recalls everything."""
+    from paper_1901_02492_amd import synth
+    s = synth.random_stack(501, n=5, h=48, w=40, n_vel=20, k=4, psf_size=5, vmax=6.0, tmax=1.0)
+    base, rows = bench.cpu_baseline(s)
+    arrays, r0, r1 = rows
+    assert r0 < r1 <= 48 and arrays["vel"].shape == (r1 - r0, 40, 12)
+    assert base["kind"] == "oracle" and base["value"] > 0 and base["cores"] >= 1
+    assert f"{r1 - r0} full-width rows" in base["sample"]
+    full = np.zeros((48, 40, 4), np.float32)
+    res = [torch.from_numpy(full.copy()), torch.from_numpy(full.copy()),
+           torch.from_numpy(full.astype(np.int32)), torch.from_numpy(full.astype(np.int16))]
+    for t, key in zip(res, ("nu", "alpha", "vel", "nobs")):
+        t[r0:r1] = torch.from_numpy(np.ascontiguousarray(arrays[key][..., :4]).astype(
+            t.numpy().dtype))
+    rec = bench.recall_vs_fp64(rows, res, 4)
+    assert rec["value"] == 1.0 and rec["pixels"] == (r1 - r0) * 40
