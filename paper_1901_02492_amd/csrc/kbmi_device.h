@@ -31,6 +31,12 @@
 #ifndef KBMI_PERSIST_BS
 #define KBMI_PERSIST_BS 2       // float32 planes: tiles per block row in the persistent order (0: off)
 #endif
+#ifndef KBMI_PIPE_MAX_LP
+#define KBMI_PIPE_MAX_LP 56     // 16-bit planes: longest list with two velocities' gathers in flight
+#endif
+#ifndef KBMI_PERSIST_LP
+#define KBMI_PERSIST_LP 0       // 16-bit planes also take the persistent order
+#endif
 #ifndef KBMI_PERSIST_SPIN
 #define KBMI_PERSIST_SPIN 4000  // bound of a wave's wait at a generation boundary
 #endif
@@ -42,7 +48,10 @@
 #define KBMI_NET_MAX_F32 64     // longest list merged by the comparator network (float32)
 #endif
 #ifndef KBMI_NET_MAX_LP
-#define KBMI_NET_MAX_LP 64      // 16-bit planes (past 50 their scales move to LDS)
+#define KBMI_NET_MAX_LP 64      // 16-bit planes
+#endif
+#ifndef KBMI_LP_SC_MIN_KM
+#define KBMI_LP_SC_MIN_KM 0     // 16-bit planes: lists of at least this length read their scales from LDS
 #endif
 #ifndef KBMI_INTERIOR
 #define KBMI_INTERIOR 1         // float32: start rows with every displaced row in frame skip the row check
@@ -721,7 +730,8 @@ __device__ __forceinline__ void visit_velocities(
         // fetched behind them (into the registers the row of jj+1 just left).
         // The load buffers alternate, so the loop runs in pairs of visits; a
         // visit past the end repeats the last row and is never scored.
-        hoist_image0(ss0[0].x, ss0[0].y);
+        if constexpr (LDS_SC) hoist_image0(sc_lds[0], sc_lds[1]);
+        else hoist_image0(ss0[0].x, ss0[0].y);
         i32x4 e[NB];
         LoadT va[NB], vb[NB];
         fetch(0, 0, e);
@@ -739,7 +749,13 @@ __device__ __forceinline__ void visit_velocities(
             const int j2 = visit[n2];
             __builtin_amdgcn_sched_barrier(0);
             float P = P0, F = F0;
-            accumulate(ss0, cur, P, F, 1);
+            if constexpr (LDS_SC) {
+                Scales ss = {};
+                lds_scales(0, ss);
+                accumulate(ss, cur, P, F, 1);
+            } else {
+                accumulate(ss0, cur, P, F, 1);
+            }
             finish(j_cur, P, F, c0 + count(cur, 1));
             j_cur = j_nxt;
             j_nxt = j2;
@@ -888,10 +904,13 @@ __device__ __forceinline__ void search_tile(
         if (__any(nq == PB)) merge_queue();
     };
 
-    // Two velocities' gathers fit beside the list up to KM = 50 (measured:
-    // longer lists spill registers with the second load buffer).
-    visit_velocities<NB, FMT, PF, (KBMI_PIPELINE != 0 && KM <= 50), MB, INTERIOR,
-                     (FMT != KB_F32 && KM > 50)>(
+    // Two velocities' gathers fit beside the list up to KM = 50 with float32
+    // loads and up to KM = 56 with 16-bit loads, whose scales then sit in LDS
+    // (longer lists spill registers with the second load buffer).
+    visit_velocities<NB, FMT, PF,
+                     (KBMI_PIPELINE != 0 && KM <= (FMT == KB_F32 ? 50 : KBMI_PIPE_MAX_LP)), MB,
+                     INTERIOR,
+                     (FMT != KB_F32 && KM >= KBMI_LP_SC_MIN_KM)>(
         reinterpret_cast<float *>(lds + search_queue_words<KM, PB>()), planes, inv_scale, n_img,
         h, w, disp, disp_stride, vel_index, n_vel, row, seg, finish);
     merge_queue();
