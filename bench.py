@@ -548,6 +548,19 @@ def lcfilter_bench(args):
     kept = out[2].to(torch.int64).sum().item()
     log(f"{args.steps} timed steps: {ms_step:.2f} ms/step, filter call {kern_ms:.2f} ms; "
         f"mean kept observations {kept / ncand:.3f}")
+    # After the timed steps: how many observations the filter dropped (one
+    # filter round per drop, plus the last), from the rejection masks.
+    rej = lib.lightcurve_filter(planes, s.t, s.vel, res[2], sigma_cut=LC_SIGMA_CUT, q=LC_Q,
+                                out=out, workspace=ws, rejected=True)[3]
+    nbits = torch.zeros_like(rej, dtype=torch.int32)
+    for i in range(n):
+        nbits += ((rej >> i) & 1).to(torch.int32)
+    hist = torch.bincount(nbits.reshape(-1).to(torch.int64), minlength=4).cpu().numpy()
+    drops = {"candidates_with_drops": int(ncand - hist[0]), "one": int(hist[1]),
+             "two": int(hist[2]), "three_or_more": int(hist[3:].sum()),
+             "observations_dropped": int((np.arange(hist.size) * hist).sum())}
+    del rej, nbits
+    log(f"drops: {drops}")
     # Algorithmic bytes per candidate: its velocity index (4), one (psi, phi)
     # pair per image (8 N), outputs nu, alpha (4 + 4) and n_obs (2).
     bytes_per_cand = 4 + 8 * n + 10
@@ -574,6 +587,7 @@ def lcfilter_bench(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "kernel_ms": kern_ms, "bytes_per_candidate": bytes_per_cand},
         "cpu_baseline": cpu,
+        "drops": drops,
     }
     print(json.dumps(line), flush=True)
 

@@ -36,105 +36,116 @@ namespace kbmi {
 namespace {
 
 constexpr int LC_THREADS = 256;
-constexpr int LC_PAIRS = 4096;                       // pairs of a grouped workgroup, at most
-constexpr int LC_MAXQ = LC_PAIRS / GR_THREADS;       // pairs per thread, at most
+constexpr int LC_PAIRS = 4032;                       // pairs of a grouped workgroup, at most
+constexpr int LC_MAXQ = (LC_PAIRS + GR_THREADS - 1) / GR_THREADS;   // pairs per thread, at most
 constexpr int LC_PX = 64;                            // start pixels per grouped tile, at most
 static_assert(LC_THREADS == GR_THREADS, "the grouped filter uses the shared grouping");
 
-// The filter of one candidate c (start pixel p, velocity index j; an index
-// outside [0, n_vel) has no observation).
+// The light curve of candidate (start pixel p, velocity index j; an index
+// outside [0, n_vel) has no observation) into v; returns the observed images'
+// bits.  Every image's load is issued before any is used (an out-of-frame or
+// missing term reads pixel 0 and is then replaced by +0), so the loads of a
+// light curve are in flight together.
 template <int NB>
-__device__ __forceinline__ void filter_candidate(int64_t c, int64_t p, int j, int h, int w, int n_img,
-                                        const float2 *__restrict__ planes,
-                                        const double *__restrict__ tau,
-                                        const double2 *__restrict__ vels, int n_vel, double c2,
-                                        double q, float *__restrict__ nu,
-                                        float *__restrict__ alpha, int16_t *__restrict__ nobs,
-                                        uint64_t *__restrict__ rejected) {
-#pragma clang fp contract(off)
-    float2 v[NB];
+__device__ __forceinline__ uint64_t gather_light_curve(int64_t p, int j, int h, int w, int n_img,
+                                                       const float2 *__restrict__ planes,
+                                                       const double *__restrict__ tau,
+                                                       const double2 *__restrict__ vels,
+                                                       int n_vel, float2 (&v)[NB]) {
+    const bool has = j >= 0 && j < n_vel;
+    const double2 vj = vels[has ? j : 0];
+    const int y0 = (int)(p / w), x0 = (int)(p - (int64_t)y0 * w);
+    bool ok[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const double ti = tau[i < n_img ? i : 0];
+        const int y = y0 + displacement(vj.y, ti, h);
+        const int x = x0 + displacement(vj.x, ti, w);
+        ok[i] = has && i < n_img && (unsigned)y < (unsigned)h && (unsigned)x < (unsigned)w;
+        const size_t at = ok[i] ? ((size_t)i * h + y) * (size_t)w + x : 0;
+        v[i] = planes[at];
+    }
     uint64_t obs = 0;   // bit i: image i observes the trajectory
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = make_float2(0.f, 0.f);
-    if (j >= 0 && j < n_vel) {
-        const int y0 = (int)(p / w), x0 = (int)(p - (int64_t)y0 * w);
-        const double2 vj = vels[j];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            if (i < n_img) {
-                const double ti = tau[i];
-                const int y = y0 + displacement(vj.y, ti, h);
-                const int x = x0 + displacement(vj.x, ti, w);
-                if ((unsigned)y < (unsigned)h && (unsigned)x < (unsigned)w) {
-                    v[i] = planes[((size_t)i * h + y) * (size_t)w + x];
-                    // Validity is carried by phi's bits: invalid pixels hold +0.
-                    if (__float_as_uint(v[i].y) != 0u) obs |= uint64_t(1) << i;
-                }
-            }
-        }
+    for (int i = 0; i < NB; ++i) {
+        if (!ok[i]) v[i] = make_float2(0.f, 0.f);
+        // Validity is carried by phi's bits: invalid pixels hold +0.
+        if (__float_as_uint(v[i].y) != 0u) obs |= uint64_t(1) << i;
     }
+    return obs;
+}
 
-    uint64_t keep = obs;
+// One round of the filter over the kept observations: the largest squared
+// standardised residual (-1 if none is kept) and, in `worst`, its image (the
+// lowest among equal values).
+template <int NB>
+__device__ __forceinline__ double filter_round(const float2 (&v)[NB], uint64_t keep,
+                                               const double *__restrict__ tau, double q,
+                                               int &worst) {
+#pragma clang fp contract(off)
     const bool walk = q > 0.0;
-    for (;;) {
-        double Jf[NB], Hf[NB];
-        double J = 0.0, H = 0.0, tp = 0.0;
-        bool seen = false;
+    double Jf[NB], Hf[NB];
+    double J = 0.0, H = 0.0, tp = 0.0;
+    bool seen = false;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            if ((keep >> i) & 1u) {
-                const double ti = tau[i];
-                if (seen && walk) {
-                    const double s = q * (ti - tp);
-                    const double d = 1.0 + s * J;
-                    J = J / d;
-                    H = H / d;
-                }
-                Jf[i] = J;
-                Hf[i] = H;
-                J = J + (double)v[i].y;
-                H = H + (double)v[i].x;
-                tp = ti;
-                seen = true;
+    for (int i = 0; i < NB; ++i) {
+        if ((keep >> i) & 1u) {
+            const double ti = tau[i];
+            if (seen && walk) {
+                const double s = q * (ti - tp);
+                const double d = 1.0 + s * J;
+                J = J / d;
+                H = H / d;
             }
+            Jf[i] = J;
+            Hf[i] = H;
+            J = J + (double)v[i].y;
+            H = H + (double)v[i].x;
+            tp = ti;
+            seen = true;
         }
-        J = 0.0;
-        H = 0.0;
-        tp = 0.0;
-        seen = false;
-        double rmax = -1.0;
-        int worst = 0;
-#pragma unroll
-        for (int i = NB - 1; i >= 0; --i) {
-            if ((keep >> i) & 1u) {
-                const double ti = tau[i];
-                if (seen && walk) {
-                    const double s = q * (tp - ti);
-                    const double d = 1.0 + s * J;
-                    J = J / d;
-                    H = H / d;
-                }
-                const double ps = (double)v[i].x, ph = (double)v[i].y;
-                const double Jk = Jf[i] + J, Hk = Hf[i] + H;
-                const double a = ps * Jk - ph * Hk;
-                const double dv = (ph * Jk) * (Jk + ph);
-                const double r = dv > 0.0 ? (a * a) / dv : 0.0;
-                if (r >= rmax) {    // descending i: the lowest index wins a tie
-                    rmax = r;
-                    worst = i;
-                }
-                J = J + ph;
-                H = H + ps;
-                tp = ti;
-                seen = true;
-            }
-        }
-        if (!(rmax > c2)) break;
-        keep &= ~(uint64_t(1) << worst);   // at most popcount(obs) iterations
     }
+    J = 0.0;
+    H = 0.0;
+    tp = 0.0;
+    seen = false;
+    double rmax = -1.0;
+    worst = 0;
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+        if ((keep >> i) & 1u) {
+            const double ti = tau[i];
+            if (seen && walk) {
+                const double s = q * (tp - ti);
+                const double d = 1.0 + s * J;
+                J = J / d;
+                H = H / d;
+            }
+            const double ps = (double)v[i].x, ph = (double)v[i].y;
+            const double Jk = Jf[i] + J, Hk = Hf[i] + H;
+            const double a = ps * Jk - ph * Hk;
+            const double dv = (ph * Jk) * (Jk + ph);
+            const double r = dv > 0.0 ? (a * a) / dv : 0.0;
+            if (r >= rmax) {    // descending i: the lowest index wins a tie
+                rmax = r;
+                worst = i;
+            }
+            J = J + ph;
+            H = H + ps;
+            tp = ti;
+            seen = true;
+        }
+    }
+    return rmax;
+}
 
+// The refit from the kept observations, summed in image order in double.
+template <int NB>
+__device__ __forceinline__ void refit(const float2 (&v)[NB], uint64_t keep, float &out_nu,
+                                      float &out_al, int &n) {
+#pragma clang fp contract(off)
     double P = 0.0, F = 0.0;
-    int n = 0;
+    n = 0;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         if ((keep >> i) & 1u) {
@@ -143,15 +154,12 @@ __device__ __forceinline__ void filter_candidate(int64_t c, int64_t p, int j, in
             ++n;
         }
     }
-    float out_nu = -INFINITY, out_al = 0.f;
+    out_nu = -INFINITY;
+    out_al = 0.f;
     if (F > 0.0) {
         out_nu = (float)(P / sqrt(F));
         out_al = (float)(P / F);
     }
-    nu[c] = out_nu;
-    alpha[c] = out_al;
-    nobs[c] = (int16_t)n;
-    if (rejected) rejected[c] = obs & ~keep;
 }
 
 // One thread per candidate, in list order (lists longer than LC_PAIRS).
@@ -163,14 +171,49 @@ __global__ __launch_bounds__(LC_THREADS) void lightcurve_kernel(
     float *__restrict__ alpha, int16_t *__restrict__ nobs, uint64_t *__restrict__ rejected) {
     const int64_t c = (int64_t)blockIdx.x * LC_THREADS + threadIdx.x;
     if (c >= ncand) return;
-    filter_candidate<NB>(c, c / k, cand_vel[c], h, w, n_img, planes, tau, vels, n_vel, c2, q,
-                         nu, alpha, nobs, rejected);
+    float2 v[NB];
+    const uint64_t obs =
+        gather_light_curve<NB>(c / k, cand_vel[c], h, w, n_img, planes, tau, vels, n_vel, v);
+    uint64_t keep = obs;
+    for (;;) {   // at most popcount(obs) + 1 rounds
+        int worst;
+        if (!(filter_round<NB>(v, keep, tau, q, worst) > c2)) break;
+        keep &= ~(uint64_t(1) << worst);
+    }
+    float o_nu, o_al;
+    int n;
+    refit<NB>(v, keep, o_nu, o_al, n);
+    nu[c] = o_nu;
+    alpha[c] = o_al;
+    nobs[c] = (int16_t)n;
+    if (rejected) rejected[c] = obs & ~keep;
+}
+
+// LDS of a grouped workgroup for np_max pairs: per pair its velocity index
+// (then its nu), alpha, grouped order, two queue slots and n_obs, then the
+// grouping state.
+size_t lightcurve_lds_bytes(int np_max) {
+    return (((size_t)np_max * (4 + 4 + 2 + 2 + 2 + 1) + 15) & ~(size_t)15) + 16 +
+           group_lds_bytes();
 }
 
 // A workgroup per tile of pt start pixels of one row and their pt * k
 // candidates, grouped by velocity before they are gathered (the re-score's
 // grouping); XCD x walks down tile columns x, x + 8, ... as the re-score
 // does, so the eight XCDs sweep adjacent columns at about the same rows.
+//
+// The lanes of a wave filter different candidates in step, so a lane that
+// drops an observation holds its whole wave for another round, and on
+// workloads where most candidates drop one observation nearly every wave runs
+// two or three rounds.  With NB = 16 the rounds are therefore taken in
+// passes: pass 0 runs the first round of every candidate; a candidate that
+// drops an observation is queued, and pass p runs round p + 1 of the queued
+// candidates (regathering their light curves) until the queue is empty.  Each
+// candidate still runs the same rounds in the same order, so its results do
+// not change.  A pass-0 queue entry holds the pair and the image it dropped;
+// later entries hold the pair, with its dropped images in the grouped-order
+// slot it no longer needs.  Results are staged in LDS and written as
+// contiguous runs of the tile's candidates.
 template <int NB>
 __global__ __launch_bounds__(LC_THREADS, NB == 16 ? 3 : 1) void lightcurve_grouped_kernel(
     int k, int pt, int h, int w, int row0, int n_rows, int n_img,
@@ -178,9 +221,17 @@ __global__ __launch_bounds__(LC_THREADS, NB == 16 ? 3 : 1) void lightcurve_group
     const double2 *__restrict__ vels, int n_vel, double c2, double q,
     const int32_t *__restrict__ cand_vel, float *__restrict__ nu, float *__restrict__ alpha,
     int16_t *__restrict__ nobs, uint64_t *__restrict__ rejected) {
-    __shared__ int32_t s_vj[LC_PAIRS];
-    __shared__ uint16_t s_ord[LC_PAIRS];
-    __shared__ uint32_t s_bin[GR_BINS + 8];
+    extern __shared__ __align__(16) unsigned char lc_lds[];
+    const int np_max = pt * k;
+    int32_t *s_vj = reinterpret_cast<int32_t *>(lc_lds);   // velocity index, then nu (bits)
+    float *s_al = reinterpret_cast<float *>(lc_lds + (size_t)np_max * 4);
+    uint16_t *s_ord = reinterpret_cast<uint16_t *>(lc_lds + (size_t)np_max * 8);
+    uint16_t *s_q0 = s_ord + np_max;
+    uint16_t *s_q1 = s_q0 + np_max;
+    uint8_t *s_no = reinterpret_cast<uint8_t *>(s_q1 + np_max);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(lc_lds + (((size_t)np_max * 15 + 15) & ~15ull));
+    uint32_t *s_bin = s_cnt + 4;
+    static_assert(LC_PAIRS <= 4096, "a queue entry holds a 12-bit pair index");
     const int n_ct = (w + pt - 1) / pt;
     const int64_t kb = (int64_t)(blockIdx.x >> 3);
     const int64_t ct64 = 8 * (kb / n_rows) + (int64_t)(blockIdx.x & 7u);
@@ -192,22 +243,83 @@ __global__ __launch_bounds__(LC_THREADS, NB == 16 ? 3 : 1) void lightcurve_group
     const int np = npx * k;
     const int t = (int)threadIdx.x;
     const int64_t c0 = p0 * (int64_t)k;
+    if (t < 2) s_cnt[t] = 0u;   // queue lengths (the grouping's barriers publish them)
     const int n_sorted = group_pairs_by_velocity<LC_MAXQ>(cand_vel + c0, np, n_vel, s_vj, s_ord,
                                                           s_bin, s_bin + GR_BINS);
-    for (int pos = t; pos < n_sorted; pos += LC_THREADS) {
-        const int qq = s_ord[pos];
-        filter_candidate<NB>(c0 + qq, p0 + qq / k, s_vj[qq], h, w, n_img, planes, tau, vels,
-                             n_vel, c2, q, nu, alpha, nobs, rejected);
-    }
-    // Candidates whose index is outside the grid have no observation: what
-    // filter_candidate gives them (nu = -inf, alpha = 0, nothing kept).
+    // Candidates whose index is outside the grid have no observation:
+    // nu = -inf, alpha = 0, nothing kept.
     for (int qq = t; qq < np; qq += LC_THREADS)
         if (s_vj[qq] < 0) {
-            nu[c0 + qq] = -INFINITY;
-            alpha[c0 + qq] = 0.f;
-            nobs[c0 + qq] = 0;
+            s_vj[qq] = (int32_t)__float_as_uint(-INFINITY);
+            s_al[qq] = 0.f;
+            s_no[qq] = 0;
             if (rejected) rejected[c0 + qq] = 0;
         }
+    int n_items = n_sorted;
+#pragma unroll 1
+    for (int pass = 0; n_items > 0; ++pass) {
+        uint16_t *q_in = (pass & 1) ? s_q0 : s_q1;    // read by passes >= 1
+        uint16_t *q_out = (pass & 1) ? s_q1 : s_q0;
+        uint32_t *n_out = s_cnt + (pass & 1);
+        for (int it = t; it < n_items; it += LC_THREADS) {
+            int qq;
+            uint64_t dropped = 0;
+            if (pass == 0) {
+                qq = s_ord[it];
+            } else if (pass == 1) {
+                const uint32_t e = q_in[it];
+                qq = (int)(e & 0xFFFu);
+                dropped = uint64_t(1) << (e >> 12);
+            } else {
+                qq = q_in[it];
+                dropped = s_ord[qq];
+            }
+            float2 v[NB];
+            const uint64_t obs = gather_light_curve<NB>(p0 + qq / k, s_vj[qq], h, w, n_img,
+                                                        planes, tau, vels, n_vel, v);
+            uint64_t keep = obs & ~dropped;
+            bool queued = false;
+            for (;;) {   // at most popcount(obs) + 1 rounds
+                int worst;
+                if (!(filter_round<NB>(v, keep, tau, q, worst) > c2)) break;
+                keep &= ~(uint64_t(1) << worst);
+                if constexpr (NB == 16) {
+                    // The next round in the next pass.
+                    const uint32_t slot = atomicAdd(n_out, 1u);
+                    if (pass == 0) {
+                        q_out[slot] = (uint16_t)(qq | (worst << 12));
+                    } else {
+                        s_ord[qq] = (uint16_t)(obs & ~keep);
+                        q_out[slot] = (uint16_t)qq;
+                    }
+                    queued = true;
+                    break;
+                }
+            }
+            if (!queued) {
+                float o_nu, o_al;
+                int n;
+                refit<NB>(v, keep, o_nu, o_al, n);
+                s_vj[qq] = (int32_t)__float_as_uint(o_nu);
+                s_al[qq] = o_al;
+                s_no[qq] = (uint8_t)n;
+                if (rejected) rejected[c0 + qq] = obs & ~keep;
+            }
+        }
+        __syncthreads();
+        if constexpr (NB == 16) {
+            n_items = (int)*n_out;
+            __syncthreads();              // every thread has read the count
+            if (t == 0) *n_out = 0u;      // this counter serves pass + 2
+        } else {
+            n_items = 0;
+        }
+    }
+    for (int qq = t; qq < np; qq += LC_THREADS) {
+        nu[c0 + qq] = __uint_as_float((uint32_t)s_vj[qq]);
+        alpha[c0 + qq] = s_al[qq];
+        nobs[c0 + qq] = (int16_t)s_no[qq];
+    }
 }
 
 template <int NB>
@@ -231,8 +343,9 @@ kb_status launch_lightcurve(int64_t ncand, int k, int h, int w, int n_img, const
     for (int64_t r0 = 0; r0 < h; r0 += max_rows) {
         const int n_rows = (int)std::min<int64_t>(max_rows, h - r0);
         hipLaunchKernelGGL(lightcurve_grouped_kernel<NB>, dim3((unsigned)(per_row * n_rows)),
-                           dim3(LC_THREADS), 0, s, k, pt, h, w, (int)r0, n_rows, n_img, planes,
-                           tau, vels, n_vel, c2, q, cv, nu, al, no, rej);
+                           dim3(LC_THREADS), lightcurve_lds_bytes(pt * k), s, k, pt, h, w,
+                           (int)r0, n_rows, n_img, planes, tau, vels, n_vel, c2, q, cv, nu, al,
+                           no, rej);
         const kb_status st = launch_status("lightcurve_grouped_kernel");
         if (st != KB_OK) return st;
     }

@@ -37,13 +37,20 @@ __device__ inline int group_pairs_by_velocity(const int32_t *__restrict__ cv, in
     __syncthreads();
 
     // Count pairs per bin; remember each pair's bin and place within it.
+    // The thread's indices are all loaded before the first is used.
+    int32_t jv[MAXQ];
+#pragma unroll
+    for (int r = 0; r < MAXQ; ++r) {
+        const int q = t + r * GR_THREADS;
+        jv[r] = q < np ? cv[q] : -1;
+    }
     uint32_t slot[MAXQ];
 #pragma unroll
     for (int r = 0; r < MAXQ; ++r) {
         const int q = t + r * GR_THREADS;
         slot[r] = 0xFFFFFFFFu;
         if (q < np) {
-            const int32_t j = cv[q];
+            const int32_t j = jv[r];
             const bool ok = j >= 0 && j < n_vel;
             vj[q] = ok ? j : -1;
             if (ok) {
