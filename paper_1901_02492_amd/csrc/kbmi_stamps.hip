@@ -88,23 +88,35 @@ __global__ __launch_bounds__(ST_THREADS) void stamp_kernel(
         const int a = e / side, b = e - a * side;
         double acc = 0.0;
         int cnt = 0;
+        // Images in groups of 16: a group's loads are all issued before the
+        // first is used (a term that is not read loads element 0 and is then
+        // skipped), then its terms are added in image order.
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            if ((use >> i) & 1u) {
+        for (int i0 = 0; i0 < NB; i0 += 16) {
+            float im[16], va[16];
+            uint8_t mk[16];
+            bool in[16];
+#pragma unroll
+            for (int b16 = 0; b16 < 16; ++b16) {
+                const int i = i0 + b16;
                 const int64_t yy = (int64_t)hit.y + dy[i] + (a - R);
                 const int64_t xx = (int64_t)hit.x + dx[i] + (b - R);
-                if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
-                    const size_t p = ((size_t)i * h + yy) * (size_t)w + xx;
-                    const float im = img[p];
-                    const float va = var[p];
-                    const bool valid = (mask == nullptr || mask[p] == 0) && isfinite(im) &&
-                                       isfinite(va) && va > 0.f;
-                    if (valid) {
-                        acc = acc + (double)im;
-                        ++cnt;
-                    }
+                in[b16] = ((use >> i) & 1u) && yy >= 0 && yy < h && xx >= 0 && xx < w;
+                const size_t p = in[b16] ? ((size_t)i * h + yy) * (size_t)w + xx : 0;
+                im[b16] = img[p];
+                va[b16] = var[p];
+                mk[b16] = mask ? mask[p] : 0;
+            }
+#pragma unroll
+            for (int b16 = 0; b16 < 16; ++b16) {
+                const bool valid = in[b16] && mk[b16] == 0 && isfinite(im[b16]) &&
+                                   isfinite(va[b16]) && va[b16] > 0.f;
+                if (valid) {
+                    acc = acc + (double)im[b16];
+                    ++cnt;
                 }
             }
+            if (i0 + 16 < NB) __builtin_amdgcn_sched_barrier(0);
         }
         const double S = cnt > 0 ? acc / (double)cnt : 0.0;   // exact int -> double
         S_l[e] = S;
