@@ -199,6 +199,9 @@ def main():
                     choices=["survey", "small", "serve", "large", "large1", "lcfilter",
                              "hits", "threshold", "stamps", "cluster"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-one-job", action="store_true",
+                    help="survey/hits (float32): search through kb_search_batch with the stack "
+                         "as its only job instead of kb_search")
     ap.add_argument("--precision", default="f32", choices=["f32", "f16", "bf16"],
                     help="survey/hits: plane format searched (16-bit formats are "
                          "re-scored from the float32 planes by kb_topk)")
@@ -291,6 +294,13 @@ def main():
     cand = lib.alloc_candidates(h, w, kc, dev)
     res = lib.alloc_candidates(h, w, s.k, dev) if (lp is not None or kc != s.k) else None
     ws = lib.alloc_workspace(n, h, w, nv, dev)
+    batch_jobs = batch_ws = None
+    if args.batch_one_job:
+        if lp is not None:
+            raise SystemExit("--batch-one-job runs the float32 search")
+        batch_jobs = [dict(planes=planes, t=s.t, vel=s.vel, out=cand)]
+        batch_ws = torch.empty(max(lib.search_batch_workspace_bytes(batch_jobs), 256),
+                               dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     log("inputs resident on the device")
@@ -305,7 +315,9 @@ def main():
                              lp_scale=lp_scale)
         if ev is not None:
             ev[0].record(stream)
-        if lp is None:
+        if batch_jobs is not None:
+            lib.search_batch(batch_jobs, kc, workspace=batch_ws)
+        elif lp is None:
             lib.search(planes, s.t, s.vel, kc, out=cand, workspace=ws)
         else:
             lib.search(lp_planes, s.t, s.vel, kc, out=cand, workspace=ws, lp_scale=lp_scale)
@@ -345,14 +357,14 @@ def main():
     achieved = bytes_per_tie * tie / (search_ms * 1e-3) / 1e9
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     peak = gather_peak(torch, dev, cus, width=8 if lp is None else 4)
-    traffic = measured_traffic() if (lp is None and kc == s.k and args.workload == "survey") \
-        else None
+    traffic = measured_traffic() if (lp is None and kc == s.k and args.workload == "survey"
+                                     and batch_jobs is None) else None
     hbm_gbs = None if traffic is None else traffic / (search_ms * 1e-3) / 1e9
     if peak is not None:
         log(f"gather peak {peak['l2_gbs']:.0f} GB/s from L2 (2 waves/SIMD "
             f"{peak['l2_2wave_gbs']:.0f}), {peak['hbm_gather_gbs']:.0f} GB/s from HBM")
-        roof = {"bound": "l2", "kernel": "search_persistent_kernel" if lp is None
-                else "search_kernel", "achieved": achieved, "peak": peak["l2_gbs"],
+        roof = {"bound": "l2", "kernel": "search_batch_kernel" if batch_jobs else
+                "search_persistent_kernel" if lp is None else "search_kernel", "achieved": achieved, "peak": peak["l2_gbs"],
                 "unit": "GB/s", "frac": achieved / peak["l2_gbs"], "traffic": traffic,
                 "peak_source": f"measured in this run: kbp_gather_peak, {int(bytes_per_tie)}"
                                f"-byte-per-lane raw buffer loads (one unaligned "
@@ -393,7 +405,9 @@ def main():
                    "n_img": n, "h": h, "w": w, "n_vel": nv, "k": s.k, "k_cand": kc,
                    "trajectories": h * w * nv, "tie_per_step": tie,
                    "step": ("kb_mask_bright + " if bright is not None else "")
-                           + "kb_make_psi_phi + kb_search + kb_topk"
+                           + "kb_make_psi_phi + "
+                           + ("kb_search_batch (one job)" if batch_jobs else "kb_search")
+                           + " + kb_topk"
                            + (" (re-score from f32 planes)" if lp is not None else
                               " (in place)" if kc == s.k else ""),
                    "bright_threshold": bright},
@@ -408,6 +422,29 @@ def main():
     if lp is not None:
         out["precision"] = precision_vs_f32(lib, torch, planes, cand, res, s, kc, ws)
     print(json.dumps(out), flush=True)
+
+
+def topk_agreement(torch, ref, got, k, chunk_rows=64):
+    """(found, equal) of two top-k result tuples (nu, alpha, vel, nobs)
+    [H][W][k]: how many of ref's entries (pixel, velocity) are in got's list
+    of the same pixel, and whether every such shared entry has bitwise equal
+    nu, alpha, vel and nobs."""
+    h = ref[2].shape[0]
+    found = 0
+    equal = True
+    for r0 in range(0, h, chunk_rows):
+        r1 = min(h, r0 + chunk_rows)
+        rv, gv = ref[2][r0:r1].reshape(-1, k), got[2][r0:r1].reshape(-1, k)
+        hit = rv[:, :, None] == gv[:, None, :]                 # [pixels, k ref, k got]
+        found += int(hit.any(-1).sum())
+        for fr, fg in zip(ref, got):
+            a = fr[r0:r1].reshape(-1, k)
+            b = fg[r0:r1].reshape(-1, k)
+            if a.dtype == torch.float32:
+                a, b = a.view(torch.int32), b.view(torch.int32)
+            same = (a[:, :, None] == b[:, None, :])
+            equal &= bool(torch.equal(same & hit, hit))
+    return found, equal
 
 
 def precision_vs_f32(lib, torch, planes, cand, res, s, kc, ws, row_stride=64, chunk_rows=64):
@@ -425,20 +462,7 @@ def precision_vs_f32(lib, torch, planes, cand, res, s, kc, ws, row_stride=64, ch
     ref = lib.topk(lib.search(planes, s.t, s.vel, k, workspace=ws), k, n)
     full = lib.topk(cand, kc, n, rescore=(planes, s.t, s.vel, ws))   # f32 values of every candidate
     torch.cuda.synchronize()
-    found = 0
-    equal = True
-    for r0 in range(0, h, chunk_rows):
-        r1 = min(h, r0 + chunk_rows)
-        rv, gv = ref[2][r0:r1].reshape(-1, k), res[2][r0:r1].reshape(-1, k)
-        hit = rv[:, :, None] == gv[:, None, :]                 # [pixels, k ref, k got]
-        found += int(hit.any(-1).sum())
-        for fr, fg in zip(ref, res):
-            a = fr[r0:r1].reshape(-1, k)
-            b = fg[r0:r1].reshape(-1, k)
-            if a.dtype == torch.float32:
-                a, b = a.view(torch.int32), b.view(torch.int32)
-            same = (a[:, :, None] == b[:, None, :])
-            equal &= bool(torch.equal(same & hit, hit))
+    found, equal = topk_agreement(torch, ref, res, k, chunk_rows)
     rows = torch.arange(0, h, row_stride, device=planes.device)
     c_nu, c_al, c_v = (t[rows].reshape(-1, kc) for t in cand[:3])
     f_nu, f_al, f_v = (t[rows].reshape(-1, kc) for t in full[:3])
@@ -1076,6 +1100,7 @@ def serve_bench(args):
     # outstanding, 16-bit search with FP32 re-score, then plain FP32.
     n_req = args.requests or 6
     res = {}
+    first = {}
     for lp in ("f16", None):
         reqs = [_survey_request(serve, synth, dev, q, 25, 4096, 4096, 50, 80,
                                 seed=synth.SEED_BASE + 4000 + q, src_per_16m=300.0,
@@ -1090,6 +1115,8 @@ def serve_bench(args):
             f = pending.pop(0)
             d = f.result()
             lat.append(d.latency)
+            if len(lat) == 1:
+                first[lp or "f32"] = d.result     # request 0, kept for the comparison
             d.result = None
             if nxt < n_req:
                 pending.append(srv.submit(reqs[nxt]))
@@ -1100,6 +1127,14 @@ def serve_bench(args):
         res[lp or "f32"] = {"value": tie / (t1 - t0), "latency_s": _quantiles(lat),
                             "wall_s": t1 - t0}
         log(f"large {lp or 'f32'}: {tie / (t1 - t0):.3e} TIE/s")
+    # Request 0 in FP16 + re-score against the same request in FP32.
+    found, equal = topk_agreement(torch, first["f32"], first["f16"], 50)
+    hw = first["f32"][2].shape[0] * first["f32"][2].shape[1]
+    agreement = {"request": 0, "recall_vs_f32": found / (hw * 50), "pixels": hw,
+                 "kept_values_bitwise_equal_f32": equal}
+    log(f"large request 0: FP16 top-50 recall against FP32 {agreement['recall_vs_f32']:.7f}, "
+        f"kept values equal: {equal}")
+    del first
     r16 = res["f16"]
     out = {
         "metric": "trajectory-image evals/s", "value": r16["value"],
@@ -1116,6 +1151,7 @@ def serve_bench(args):
                      "frac": 4.0 * r16["value"] / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_tie": 4.0},
         "f32_same_requests": res["f32"],
+        "precision": agreement,
     }
     print(json.dumps(out), flush=True)
 

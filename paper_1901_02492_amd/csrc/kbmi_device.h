@@ -500,13 +500,19 @@ __device__ __forceinline__ void visit_velocities(
     // (which may point outside the planes) is never dereferenced.  no_entry0:
     // entry 0 (image 0, whose pair is loaded once per tile) gets a zero-length
     // buffer too, so its load touches no memory.
-    // nl: entries of this batch that hold images (later ones are padding):
-    // their loads are not issued and their registers hold 0.
+    // nl: entries of this batch that hold images (later ones are padding).
+    // Float32 planes skip the padding slots' loads (their registers hold 0).
+    // 16-bit planes issue them like the others: a padding entry's column
+    // x0 + w fails the range check (and its row, outside the frame, gets a
+    // zero-length buffer off interior tiles), so the load returns 0 and
+    // touches no memory; with no branch, the wait before a batch's sums counts
+    // exactly the loads of the batch behind it (25 images at 4000 velocities:
+    // 16-bit 974 -> 889 ms; float32 902 -> 1655 ms, so float32 keeps the skip).
     auto issue = [&](const i32x4(&e)[NB], LoadT(&v)[NB], int from, bool no_entry0, int nl) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             if (b < from) continue;
-            if (b >= nl) {
+            if (FMT == KB_F32 && b >= nl) {
                 v[b] = LoadT{};
                 continue;
             }
