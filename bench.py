@@ -781,6 +781,18 @@ def threshold_bench(args):
         f"{nh} hits, clustering {cluster_ms:.2f} ms, {groups} groups")
     tie = s.tie
     achieved = BYTES_PER_TIE_F32 * tie / (search_ms * 1e-3) / 1e9
+    # The same bound as the top-k search's: the measured gather peak.
+    peak = gather_peak(torch, dev, torch.cuda.get_device_properties(dev).multi_processor_count)
+    roof = {"bound": "hbm", "kernel": "search_threshold_persistent_kernel", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None}
+    if peak is not None:
+        roof.update({"bound": "l2", "peak": peak["l2_gbs"], "frac": achieved / peak["l2_gbs"],
+                     "peak_source": "measured in this run: kbp_gather_peak (8-byte-per-lane "
+                                    "raw buffer loads, as for the top-k search)",
+                     "peak_2wave_per_simd": peak["l2_2wave_gbs"],
+                     "hbm": {"peak": HBM_PEAK_GBS, "algorithmic_frac": achieved / HBM_PEAK_GBS}})
+    roof.update({"search_ms": search_ms, "bytes_per_tie": BYTES_PER_TIE_F32})
     line = {
         "metric": "trajectory-image evals/s",
         "value": tie / (ms_step * 1e-3),
@@ -799,10 +811,7 @@ def threshold_bench(args):
                    "n_img": n, "h": h, "w": w, "n_vel": nv, "tie_per_step": tie,
                    "hits": nh, "groups": groups, "cluster_ms": cluster_ms,
                    "step": "kb_make_psi_phi + kb_search_threshold + kb_cluster_hits"},
-        "roofline": {"bound": "hbm", "kernel": "search_threshold_kernel", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "search_ms": search_ms,
-                     "bytes_per_tie": BYTES_PER_TIE_F32},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
