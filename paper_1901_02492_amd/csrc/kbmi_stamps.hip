@@ -44,9 +44,10 @@ struct StampLimits {
 // One wave per candidate.  The lanes cover the stamp's pixels (row-major,
 // 64 at a time), so the lanes of one load read runs of adjacent pixels of one
 // image row; each lane sums its pixel over the kept images in image order.
-// The stamp goes to LDS, and lane 0 takes the moments in row-major order:
-// every value is the same sequence of double operations as one thread per
-// candidate walking the stamp.
+// The stamp goes to LDS, and lanes 0-5 take one raw moment each in row-major
+// order, with the pixel weights from a table in LDS: every value is the same
+// sequence of double operations as one thread per candidate walking the
+// stamp.
 template <int NB>
 __global__ __launch_bounds__(ST_THREADS) void stamp_kernel(
     const float *__restrict__ img, const float *__restrict__ var,
@@ -55,13 +56,26 @@ __global__ __launch_bounds__(ST_THREADS) void stamp_kernel(
     const uint64_t *__restrict__ drop, int64_t n_cand, int R, StampLimits lim,
     float *__restrict__ stamps, double *__restrict__ moments, uint8_t *__restrict__ pass) {
 #pragma clang fp contract(off)
-    extern __shared__ double s_stamp[];   // [ST_WAVES][side * side]
+    // [ST_WAVES][side * side] stamps, then the six moment weights of every
+    // stamp pixel [6][side * side]: 1, u, v, u u, v v, u v (exact in double).
+    extern __shared__ double s_stamp[];
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int64_t c = (int64_t)blockIdx.x * ST_WAVES + wave;
     const bool live = c < n_cand;
     const int side = 2 * R + 1;
     const int npix = side * side;
     double *S_l = s_stamp + (size_t)wave * npix;
+    double *W_l = s_stamp + (size_t)ST_WAVES * npix;
+    for (int e = (int)threadIdx.x; e < npix; e += ST_THREADS) {
+        const int a = e / side, b = e - a * side;
+        const double u = (double)(b - R), v = (double)(a - R);
+        W_l[e] = 1.0;
+        W_l[npix + e] = u;
+        W_l[2 * npix + e] = v;
+        W_l[3 * npix + e] = u * u;
+        W_l[4 * npix + e] = v * v;
+        W_l[5 * npix + e] = u * v;
+    }
     kb_hit hit{};
     bool ok_vel = false;
     if (live) {
@@ -123,21 +137,18 @@ __global__ __launch_bounds__(ST_THREADS) void stamp_kernel(
         if (live && stamps) stamps[c * npix + e] = (float)S;
     }
     __syncthreads();
-    if (!live || lane != 0) return;
-    double M00 = 0.0, M10 = 0.0, M01 = 0.0, M20 = 0.0, M02 = 0.0, M11 = 0.0;
-    for (int a = 0; a < side; ++a) {
-        const double v = (double)(a - R);
-        for (int b = 0; b < side; ++b) {
-            const double u = (double)(b - R);
-            const double S = S_l[a * side + b];
-            M00 = M00 + S;
-            M10 = M10 + u * S;
-            M01 = M01 + v * S;
-            M20 = M20 + (u * u) * S;
-            M02 = M02 + (v * v) * S;
-            M11 = M11 + (u * v) * S;
-        }
+    if (!live) return;
+    // Lane m < 6 accumulates raw moment m in row-major order, M += w_m * S
+    // with its weight from LDS (1 * S is S): the operations of the six sums
+    // of one pass over the stamp, six lanes at a time.
+    double M = 0.0;
+    if (lane < 6) {
+        const double *w_m = W_l + (size_t)lane * npix;
+        for (int e = 0; e < npix; ++e) M = M + w_m[e] * S_l[e];
     }
+    const double M00 = __shfl(M, 0), M10 = __shfl(M, 1), M01 = __shfl(M, 2);
+    const double M20 = __shfl(M, 3), M02 = __shfl(M, 4), M11 = __shfl(M, 5);
+    if (lane != 0) return;
     const double ub = M10 / M00, vb = M01 / M00;
     const double m20 = M20 / M00 - ub * ub;
     const double m02 = M02 / M00 - vb * vb;
@@ -165,7 +176,7 @@ kb_status launch_stamps(const float *img, const float *var, const uint8_t *mask,
                         StampLimits lim, float *stamps, double *moments, uint8_t *pass,
                         hipStream_t s) {
     const int64_t blocks = (n_cand + ST_WAVES - 1) / ST_WAVES;
-    const size_t lds = (size_t)ST_WAVES * (2 * R + 1) * (2 * R + 1) * sizeof(double);
+    const size_t lds = (size_t)(ST_WAVES + 6) * (2 * R + 1) * (2 * R + 1) * sizeof(double);
     hipLaunchKernelGGL(stamp_kernel<NB>, dim3((unsigned)blocks), dim3(ST_THREADS), lds, s, img, var,
                        mask, n_img, h, w, tau, vels, n_vel, cand, drop, n_cand, R, lim, stamps,
                        moments, pass);
