@@ -54,7 +54,7 @@
 #define KBMI_LP_SC_MIN_KM 0     // 16-bit planes: lists of at least this length read their scales from LDS
 #endif
 #ifndef KBMI_INTERIOR
-#define KBMI_INTERIOR 1         // float32: start rows with every displaced row in frame skip the row check
+#define KBMI_INTERIOR 1         // start rows with every displaced row in frame skip the row check
 #endif
 // List lengths compiled for the search (each slot costs registers and
 // compare-and-swap work on every insertion); a search keeps k_cand
@@ -519,7 +519,16 @@ __device__ __forceinline__ void visit_velocities(
             const uint64_t off = ((uint64_t)(uint32_t)e[b].w << 32) | (uint32_t)e[b].z;
             // Interior tiles: every real entry's row is in the frame; a padding
             // entry's column (x0 + w) fails the buffer's range check instead.
-            bool in_rows = INTERIOR || (unsigned)(row + e[b].y) < (unsigned)h;
+            // 16-bit planes over several batches issue up to 15 padding slots
+            // per velocity; there an entry with dy >= h (padding, or a
+            // trajectory that has left the frame, out of it for any start row)
+            // gets a zero-length buffer, because lanes that fail the range check
+            // of a non-empty buffer cost far more than a buffer that holds
+            // nothing (25 images: 1110 -> 882 ms).  Elsewhere the extra scalar
+            // compare costs more than it saves.
+            constexpr bool kPadCheck = MB && FMT != KB_F32;
+            bool in_rows = INTERIOR ? (!kPadCheck || e[b].y < h)
+                                    : (unsigned)(row + e[b].y) < (unsigned)h;
             if (b == 0) in_rows = in_rows && !no_entry0;
             const i32x4 rs = buffer_words(row0 + off, in_rows ? row_bytes : 0u);
             if constexpr (FMT == KB_F32)
@@ -963,8 +972,8 @@ __global__ __launch_bounds__(64, 2) void search_kernel(
     __shared__ uint32_t lds[search_lds_words<KM, PB>()];
     int row, seg;
     tiles.map(blockIdx.x, row, seg);
-    if (KBMI_INTERIOR && FMT == KB_F32 && row >= row_lo && row < row_hi)
-        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB, FMT == KB_F32>(
+    if (KBMI_INTERIOR && row >= row_lo && row < row_hi)
+        search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB, true>(
             lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel, k_cand,
             row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
     else
@@ -989,8 +998,8 @@ __global__ __launch_bounds__(64, 2) void search_persistent_kernel(
     for (int gen = 0; gen < pm.generations; ++gen) {
         int row, seg;
         if (pm.map(gen, (int)blockIdx.x, row, seg)) {
-            if (KBMI_INTERIOR && FMT == KB_F32 && row >= row_lo && row < row_hi)
-                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB, FMT == KB_F32>(
+            if (KBMI_INTERIOR && row >= row_lo && row < row_hi)
+                search_tile<KM, NB, PB, FMT, KBMI_PREFETCH != 0, MB, true>(
                     lds, planes, inv_scale, n_img, h, w, disp, disp_stride, vel_index, n_vel,
                     k_cand, row, seg, cand_nu, cand_alpha, cand_vel, cand_nobs);
             else
