@@ -442,8 +442,8 @@ kb_status kb_search_batch(const kb_job *jobs, int64_t n_jobs, int32_t dtype, int
  *   Limit: the stack must fit the array:
  *     kb_search_workspace_bytes(n_img, h, w, n_vel) + 8 n_img + 20 n_vel
  *     (+ up to 1 KB of alignment) <= KB_NOALLOC_SCRATCH_BYTES,
- *   e.g. n_img <= 16 with n_vel <= 31000; beyond that it returns
- *   KB_EUNSUPPORTED and enqueues nothing.
+ *   e.g. n_img <= 16 with n_vel <= 29954, n_img <= 32 with n_vel <= 15648;
+ *   beyond that it returns KB_EUNSUPPORTED and enqueues nothing.
  *   Sharing: every call on a device uses that device's one array and leaves
  *   its contents behind.  Calls on one stream are ordered by the stream;
  *   calls that overlap on one device (other streams, other host threads,

@@ -284,3 +284,22 @@ def test_stamps_argument_checks():
     st = L.kb_stamps(fake, fake, None, 65, 8, 8, tt.ctypes.data, v.ctypes.data, 4, fake, None, 5,
                      2, 1.0, 1.0, 0.5, 4.0, None, None, fake, fake, 1 << 20, None)
     assert st == lib.KB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("n_img,n_vel", [(16, 29955), (32, 15649)])
+def test_noalloc_limit_is_the_documented_one(n_img, n_vel):
+    """kb_search_noalloc refuses, before touching a device, the first stack
+    past the limits its header states (16 images with 29954 velocities, 32
+    with 15648 fit the fixed array)."""
+    L = lib.load()
+    fake = 1 << 20
+    t = np.arange(n_img, dtype=np.float64)
+    vel = np.zeros((n_vel, 2))
+    st = L.kb_search_noalloc(fake, lib.KB_F32, None, n_img, 8, 70, t.ctypes.data,
+                             vel.ctypes.data, n_vel, 4, fake, fake, fake, fake, None)
+    assert st == lib.KB_EUNSUPPORTED
+    a = lambda x: (x + 255) // 256 * 256   # noqa: E731
+    def need(nv):
+        base = a(lib.search_workspace_bytes(n_img, 8, 70, nv))
+        return a(a(a(base + 8 * n_img) + 16 * nv) + 4 * nv)
+    assert need(n_vel) > (8 << 20) >= need(n_vel - 1)   # KB_NOALLOC_SCRATCH_BYTES
