@@ -196,8 +196,9 @@ kb_status kb_search(const void *planes, int32_t dtype, const float *lp_scale,
 
 /*
  * kb_topk - final per-pixel selection: order each start pixel's k_cand
- * candidates by (nu descending, velocity index ascending) and keep the first
- * k (Sec. 2.2 asks for the trajectories maximising nu).
+ * candidates by (nu descending, velocity index ascending; entries equal in
+ * both keep their list order) and keep the first k (Sec. 2.2 asks for the
+ * trajectories maximising nu).
  *   psi_phi_f32  device float32 planes [n_img][h][w][2] to re-score every
  *                candidate from before ordering (used after a 16-bit search),
  *                or NULL to keep the candidates' scores.  A re-scored entry

@@ -218,56 +218,85 @@ __global__ __launch_bounds__(256) void lp_convert_kernel(
 
 // ---------------------------------------------------------------------------
 // Final selection.  One thread per candidate: a 256-thread block holds whole
-// pixels (256 / k_cand of them), reads their candidate runs with coalesced
-// loads, and each thread checks that its candidate precedes the next one of
-// the same pixel.  When every pixel of the block is in rank order (kb_search
-// leaves them so) the first k of each are copied out; otherwise each
-// candidate's rank is the number of candidates of its pixel that precede it.
-// In place (outputs are the candidate arrays, k == k_cand) an ordered block
-// writes nothing; every load happens before the block's barrier, so an
-// unordered block can rewrite its own entries.
+// pixels (256 / k_cand of them), reads their candidates' nu and velocity
+// index with coalesced loads, and each thread checks that its candidate
+// precedes the next one of the same pixel.  The order is (nu descending,
+// velocity index ascending); n_obs and alpha never decide it, so they are
+// read only by blocks that write.  When every pixel of the block is in rank
+// order (kb_search leaves them so) the first k of each are copied out;
+// otherwise each candidate's rank is the number of candidates of its pixel
+// that precede it (equal keys, which only a repeated velocity gives, in list
+// order).  In place (outputs are the candidate arrays, k == k_cand) an
+// ordered block reads nothing more and writes nothing; an unordered one
+// loads all its entries before the barrier that precedes its writes.  A
+// workgroup takes TK_G groups of pixels with all their loads in flight at
+// once (one group per workgroup is bound by workgroup dispatch).
 // ---------------------------------------------------------------------------
 constexpr int TK_THREADS = 256;
+constexpr int TK_G = 4;
 
 __global__ __launch_bounds__(TK_THREADS) void topk_kernel(
     int64_t npix, int k_cand, int k, bool in_place, const float *cand_nu,
     const float *cand_alpha, const int32_t *cand_vel, const int16_t *cand_nobs, float *nu,
     float *alpha, int32_t *vel, int16_t *nobs) {
-    __shared__ uint64_t s_key[TK_THREADS];
+    __shared__ uint64_t s_key[TK_G][TK_THREADS];
     const int ppb = TK_THREADS / k_cand;
     const int t = (int)threadIdx.x;
     const int lp = t / k_cand, s = t - lp * k_cand;
-    const int64_t p = (int64_t)blockIdx.x * ppb + lp;
-    const bool active = lp < ppb && p < npix;
-    uint64_t key = 0;
-    float v_nu = 0.f, v_al = 0.f;
-    int32_t v_vel = 0;
-    int16_t v_no = 0;
-    if (active) {
-        const size_t e = (size_t)p * (size_t)k_cand + (size_t)s;
-        v_nu = cand_nu[e];
-        v_al = cand_alpha[e];
-        v_vel = cand_vel[e];
-        v_no = cand_nobs[e];
-        key = make_key(v_nu, v_vel, (uint16_t)v_no);
+    int64_t p[TK_G];
+    bool active[TK_G];
+    size_t e[TK_G];
+    float v_nu[TK_G];
+    int32_t v_vel[TK_G];
+    uint64_t key[TK_G];
+#pragma unroll
+    for (int g = 0; g < TK_G; ++g) {
+        p[g] = ((int64_t)blockIdx.x * TK_G + g) * ppb + lp;
+        active[g] = lp < ppb && p[g] < npix;
+        e[g] = (size_t)p[g] * (size_t)k_cand + (size_t)s;
+        v_nu[g] = active[g] ? cand_nu[e[g]] : 0.f;
+        v_vel[g] = active[g] ? cand_vel[e[g]] : 0;
     }
-    s_key[t] = key;
+#pragma unroll
+    for (int g = 0; g < TK_G; ++g) {
+        key[g] = active[g] ? make_key(v_nu[g], v_vel[g], 0u) : 0ull;
+        s_key[g][t] = key[g];
+    }
     __syncthreads();
-    const bool out_of_order = active && s + 1 < k_cand && !(key > s_key[t + 1]);
-    int rank = s;
-    if (__syncthreads_or(out_of_order)) {
-        rank = 0;
-        for (int r = 0; r < k_cand; ++r) rank += s_key[lp * k_cand + r] > key;
-    } else if (in_place) {
-        return;
+    bool out_of_order = false;
+#pragma unroll
+    for (int g = 0; g < TK_G; ++g)
+        out_of_order |= active[g] && s + 1 < k_cand && !(key[g] > s_key[g][t + 1]);
+    const bool reorder = __syncthreads_or(out_of_order);
+    if (!reorder && in_place) return;
+    float v_al[TK_G];
+    int16_t v_no[TK_G];
+#pragma unroll
+    for (int g = 0; g < TK_G; ++g) {
+        v_al[g] = active[g] ? cand_alpha[e[g]] : 0.f;
+        v_no[g] = active[g] ? cand_nobs[e[g]] : (int16_t)0;
     }
-    if (active && rank < k) {
-        const size_t o = (size_t)p * (size_t)k + (size_t)rank;
-        nu[o] = v_nu;
-        alpha[o] = v_al;
-        vel[o] = v_vel;
-        nobs[o] = v_no;
+    int rank[TK_G];
+#pragma unroll
+    for (int g = 0; g < TK_G; ++g) {
+        rank[g] = s;
+        if (reorder) {
+            rank[g] = 0;
+            const uint64_t *pk = s_key[g] + lp * k_cand;
+            for (int r = 0; r < k_cand; ++r)
+                rank[g] += (pk[r] > key[g]) | ((pk[r] == key[g]) & (r < s));
+        }
     }
+    if (reorder && in_place) __syncthreads();   // every entry of the block is read
+#pragma unroll
+    for (int g = 0; g < TK_G; ++g)
+        if (active[g] && rank[g] < k) {
+            const size_t o = (size_t)p[g] * (size_t)k + (size_t)rank[g];
+            nu[o] = v_nu[g];
+            alpha[o] = v_al[g];
+            vel[o] = v_vel[g];
+            nobs[o] = v_no[g];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -469,7 +498,8 @@ kb_status launch_topk(int64_t npix, int k_cand, int k, bool in_place, const floa
                       const float *ca, const int32_t *cv, const int16_t *co, float *nu,
                       float *al, int32_t *vi, int16_t *no, hipStream_t stream) {
     const int64_t ppb = TK_THREADS / k_cand;
-    const int64_t blocks = (npix + ppb - 1) / ppb;
+    const int64_t groups = (npix + ppb - 1) / ppb;
+    const int64_t blocks = (groups + TK_G - 1) / TK_G;
     hipLaunchKernelGGL(topk_kernel, dim3((unsigned)blocks), dim3(TK_THREADS), 0, stream, npix,
                        k_cand, k, in_place, cn, ca, cv, co, nu, al, vi, no);
     return launch_status("topk_kernel");

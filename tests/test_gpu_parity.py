@@ -334,6 +334,29 @@ def test_topk_orders_shuffled_candidates(torch_dev, kc, k):
         assert np.array_equal(got, np.take_along_axis(src, order, -1))
 
 
+@pytest.mark.parametrize("kc,k,in_place", [(50, 50, True), (50, 20, False), (8, 8, False)])
+def test_topk_repeated_velocity_keeps_list_order(torch_dev, kc, k, in_place):
+    """Entries equal in nu and velocity index (a list that repeats a
+    velocity, which kb_search never writes) rank in list order: the result
+    equals a stable host sort by (nu descending, index ascending), alpha and
+    n_obs moving with their entry."""
+    from paper_1901_02492_amd import lib
+    torch = torch_dev
+    rng = np.random.default_rng(kc + k)
+    h, w = 19, 23
+    nu = np.round(rng.standard_normal((h, w, kc))).astype(np.float32)
+    vel = rng.integers(0, 4, (h, w, kc)).astype(np.int32)     # many repeats
+    al = rng.standard_normal((h, w, kc)).astype(np.float32)
+    no = rng.integers(0, 30, (h, w, kc)).astype(np.int16)
+    dev = torch.device("cuda:0")
+    cand = [torch.from_numpy(a).to(dev) for a in (nu, al, vel, no)]
+    out = parity.to_numpy(lib.topk(cand, k, 5, out=cand if in_place else None))
+    torch.cuda.synchronize()
+    order = np.lexsort((vel, -nu.astype(np.float64)), axis=-1)[..., :k]
+    for got, src in zip(out, (nu, al, vel, no)):
+        assert np.array_equal(got, np.take_along_axis(src, order, -1))
+
+
 @pytest.mark.parametrize("kc", [50, 64, 7, 1])
 def test_topk_in_place(torch_dev, kc):
     """kb_topk with the candidate arrays as outputs (k == k_cand): kb_search's
