@@ -508,9 +508,10 @@ __device__ __forceinline__ void visit_velocities(
     // touches no memory; with no branch, the wait before a batch's sums counts
     // exactly the loads of the batch behind it (25 images at 4000 velocities:
     // 16-bit 974 -> 889 ms; float32 902 -> 1655 ms, so float32 keeps the skip).
-    auto issue = [&](const i32x4(&e)[NB], LoadT(&v)[NB], int from, bool no_entry0, int nl) {
+    auto issue = [&](const i32x4(&e)[NB], auto &v, int from, bool no_entry0, int nl) {
+        constexpr int NV = (int)(sizeof(v) / sizeof(v[0]));   // NB, or NB / 2
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+        for (int b = 0; b < NV; ++b) {
             if (b < from) continue;
             if (FMT == KB_F32 && b >= nl) {
                 v[b] = LoadT{};
@@ -548,18 +549,20 @@ __device__ __forceinline__ void visit_velocities(
 #pragma unroll
         for (int q = 0; q < NB / 2; ++q) ss[q] = sc4[q];
     };
-    auto accumulate = [&](const Scales &ss, const LoadT(&v)[NB], float &P, float &F, int from) {
+    // v: a batch of NB loads, or NB / 2 (with as many scale pairs in ss).
+    auto accumulate = [&](const auto &ss, const auto &v, float &P, float &F, int from) {
+        constexpr int NV = (int)(sizeof(v) / sizeof(v[0]));
         if constexpr (FMT == KB_F32) {
             (void)ss;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
+            for (int b = 0; b < NV; ++b) {
                 if (b < from) continue;
                 P += __uint_as_float(v[b].x);
                 F += __uint_as_float(v[b].y);
             }
         } else {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
+            for (int b = 0; b < NV; ++b) {
                 if (b < from) continue;
                 const float isp = (b & 1) ? ss[b / 2].z : ss[b / 2].x;
                 const float isf = (b & 1) ? ss[b / 2].w : ss[b / 2].y;
@@ -569,10 +572,11 @@ __device__ __forceinline__ void visit_velocities(
         }
     };
     // n_obs: the stored phi is nonzero exactly at valid pixels; empty slots are 0.
-    auto count = [&](const LoadT(&v)[NB], int from) {
+    auto count = [&](const auto &v, int from) {
+        constexpr int NV = (int)(sizeof(v) / sizeof(v[0]));
         uint32_t c = 0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+        for (int b = 0; b < NV; ++b) {
             if (b < from) continue;
             if constexpr (FMT == KB_F32) {
                 // min(bits, 1) as one vector instruction: the compiler's
@@ -659,9 +663,79 @@ __device__ __forceinline__ void visit_velocities(
             finish(j, P, F, c);
         }
     };
+    // NB + 1 <= n_img <= NB + NB / 2 + 1 (17 to 25 images): image 0 hoisted,
+    // the other images fill one batch of NB (images 1..NB) and one of NB / 2
+    // (images NB + 1 .. NB + NB / 2), with two batches in flight: at most
+    // NB / 2 padding slots per velocity, none at 25 images, where the
+    // general sequence below issues 2 NB - 1 slots for 24 images.  The 16-bit
+    // search is bound by issued load instructions (padding slots cost as much
+    // as real ones).  Same sums in the same image order.  16-bit planes only:
+    // float32 planes skip their padding slots' loads already, and the second
+    // path spills the float32 kernels' registers.
+    auto split_path = [&]() {
+        constexpr int NH = NB / 2;
+        if constexpr (FMT != KB_F32) {
+            // Inverse scales of images 1 .. NB + NH into LDS, image 1 first, so
+            // that each batch reads whole f32x4 words (the table of scales
+            // holds 2 * table_stride(n_img) >= 2 (NB + NH + 1) floats).
+            const float *isc = reinterpret_cast<const float *>(inv_scale);
+            for (int q = lane; q < 2 * (NB + NH); q += 64) sc_lds[q] = isc[q + 2];
+            __syncthreads();
+            hoist_image0(isc[0], isc[1]);
+        } else {
+            hoist_image0(1.f, 1.f);
+        }
+        const int nl_b = n_img - 1 - NB;          // images in batch B (0 .. NH)
+        const int last = n_vel - 1;
+        auto fetch_b = [&](int jj, i32x4(&e)[NB]) {
+            const const_i32x4 *t4 = (const const_i32x4 *)(const void *)(
+                disp + (size_t)jj * disp_stride + 1 + NB);
+#pragma unroll
+            for (int b = 0; b < NH; ++b) e[b] = t4[b];
+        };
+        i32x4 e[NB];
+        LoadT va[NB], vb[NH];
+        fetch(0, 1, e);
+        issue(e, va, 0, false, NB);               // A(0): images 1 .. NB
+        fetch_b(0, e);
+        int jn = last < 1 ? last : 1;
+        for (int jj = 0; jj < n_vel; ++jj) {
+            const int j = visit[jj];
+            issue(e, vb, 0, false, nl_b);         // B(jj) behind A(jj)
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(jn, 1, e);
+            __builtin_amdgcn_sched_barrier(0);
+            float P = P0, F = F0;
+            uint32_t c = c0;
+            {
+                Scales ss = {};
+                if constexpr (FMT != KB_F32) lds_scales(0, ss);
+                accumulate(ss, va, P, F, 0);
+                c += count(va, 0);
+            }
+            issue(e, va, 0, false, NB);           // A(jj + 1) (the last repeats)
+            __builtin_amdgcn_sched_barrier(0);
+            fetch_b(jn, e);
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                f32x4 ssb[NH / 2] = {};
+                if constexpr (FMT != KB_F32) {
+                    const f32x4 *s4 = reinterpret_cast<const f32x4 *>(sc_lds + 2 * NB);
+#pragma unroll
+                    for (int q = 0; q < NH / 2; ++q) ssb[q] = s4[q];
+                }
+                accumulate(ssb, vb, P, F, 0);
+                c += count(vb, 0);
+            }
+            finish(j, P, F, c);
+            jn = jj + 2 < last ? jj + 2 : last;
+        }
+    };
     if constexpr (MB) {
         // More images than one batch (MB): launched for n_img > NB only.
-        if (kPipe && (FMT == KB_F32 || n_img <= kMaxLdsScaleImages)) {
+        if (FMT != KB_F32 && kPipe && NB == 16 && n_img <= NB + NB / 2 + 1) {
+            if constexpr (FMT != KB_F32) split_path();
+        } else if (kPipe && (FMT == KB_F32 || n_img <= kMaxLdsScaleImages)) {
             // Each velocity's table row is read as nbat batches of NB entries,
             // and the batches of all velocities form one sequence with two
             // batches in flight (the gathers of batch q+1 are issued before

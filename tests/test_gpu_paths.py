@@ -51,6 +51,10 @@ STACKS = {
     "n6_strip": (101, 6, 40, 200, 24, 6, None, None),
     "n12_strip": (102, 12, 33, 150, 20, 5, None, None),
     "n25_strip": (103, 25, 20, 130, 16, 4, None, None),
+    # 17 to 25 images: one batch of 16 and one of 8 (batch B empty at 17,
+    # partly padding at 20)
+    "n17_strip": (109, 17, 21, 140, 18, 5, None, None),
+    "n20_strip": (110, 20, 19, 150, 22, 6, None, None),
     # 16-bit planes take the super-strip order when the width is a multiple of 1024
     "n6_super": (104, 6, 24, 1024, 16, 5, None, None),
     # >= 8192 one-wave tiles at K' = 50: the float32 persistent order
@@ -89,7 +93,8 @@ def _check_plain(res, s, ref, k):
     return parity.check_topk(gpu, *parity.oracle_full_as_pixels(ref), k)
 
 
-MATRIX_F32 = ["n6_strip", "n12_strip", "n25_strip", "n12_persist", "n25_persist"]
+MATRIX_F32 = ["n6_strip", "n12_strip", "n17_strip", "n20_strip", "n25_strip", "n12_persist",
+              "n25_persist"]
 
 
 @pytest.mark.parametrize("name", MATRIX_F32)
@@ -110,7 +115,7 @@ def test_f32_paths(torch_dev, name):
     _check_plain(parity.to_numpy(res), s, ref, k)
 
 
-MATRIX_LP = ["n6_super", "n12_strip", "n25_strip", "n25_persist"]
+MATRIX_LP = ["n6_super", "n12_strip", "n17_strip", "n20_strip", "n25_strip", "n25_persist"]
 
 
 @pytest.mark.parametrize("name", MATRIX_LP)
