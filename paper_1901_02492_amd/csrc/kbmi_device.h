@@ -508,12 +508,19 @@ __device__ __forceinline__ void visit_velocities(
     // touches no memory; with no branch, the wait before a batch's sums counts
     // exactly the loads of the batch behind it (25 images at 4000 velocities:
     // 16-bit 974 -> 889 ms; float32 902 -> 1655 ms, so float32 keeps the skip).
-    auto issue = [&](const i32x4(&e)[NB], auto &v, int from, bool no_entry0, int nl) {
+    // skip_last (float32 planes): one batch holding every image but the last
+    // slot (n_img = NB - 1, the survey's 15 images): that slot's load is
+    // skipped by one uniform branch, which leaves the wait before the
+    // previous batch's sums at most one load short: 83.5 -> 80.5 ms on the
+    // survey stack.  16-bit planes issue it (the branch measured 57.8 ->
+    // 61.2 ms there).
+    auto issue = [&](const i32x4(&e)[NB], auto &v, int from, bool no_entry0, int nl,
+                     bool skip_last = false) {
         constexpr int NV = (int)(sizeof(v) / sizeof(v[0]));   // NB, or NB / 2
 #pragma unroll
         for (int b = 0; b < NV; ++b) {
             if (b < from) continue;
-            if (FMT == KB_F32 && b >= nl) {
+            if ((FMT == KB_F32 && b >= nl) || (b == NV - 1 && skip_last)) {
                 v[b] = LoadT{};
                 continue;
             }
@@ -640,6 +647,7 @@ __device__ __forceinline__ void visit_velocities(
         }
     };
     constexpr bool kPipe = PF && PIPE;
+    const bool skip_last = FMT == KB_F32 && !MB && n_img == NB - 1;
     // 16-bit planes of more than one batch keep every image's scales in LDS
     // (read per batch), up to kMaxLdsScaleImages images.
     constexpr int kMaxLdsScaleImages = kSearchScaleWords / 2;
@@ -824,14 +832,14 @@ __device__ __forceinline__ void visit_velocities(
         i32x4 e[NB];
         LoadT va[NB], vb[NB];
         fetch(0, 0, e);
-        issue(e, va, 1, false, NB);
+        issue(e, va, 1, false, NB, skip_last);
         const int last = n_vel - 1;
         int j_cur = visit[0];
         int nxt = last < 1 ? last : 1;
         fetch(nxt, 0, e);
         int j_nxt = visit[nxt];
         auto step = [&](int jj, LoadT(&cur)[NB], LoadT(&ahead)[NB]) {
-            issue(e, ahead, 1, false, NB);             // visit jj + 1
+            issue(e, ahead, 1, false, NB, skip_last);  // visit jj + 1
             __builtin_amdgcn_sched_barrier(0);
             const int n2 = jj + 2 < last ? jj + 2 : last;
             fetch(n2, 0, e);
@@ -866,7 +874,7 @@ __device__ __forceinline__ void visit_velocities(
         for (int jj = 0; jj < n_vel; ++jj) {
             const int j = j_next;
             LoadT v[NB];
-            issue(e, v, 1, false, NB);
+            issue(e, v, 1, false, NB, skip_last);
             // Keep the next row's fetch right behind the gathers (the scheduler
             // would otherwise sink it below the sums).
             __builtin_amdgcn_sched_barrier(0);
