@@ -53,6 +53,14 @@
 #ifndef KBMI_LP_SC_MIN_KM
 #define KBMI_LP_SC_MIN_KM 0     // 16-bit planes: lists of at least this length read their scales from LDS
 #endif
+// Float32, one batch of images: how many trailing padding slots may be
+// skipped by uniform branches.  1: the survey's 15 images skip their one
+// padding slot (83.5 -> 80.5 ms).  3 also serves 13 and 14 images (13 x
+// 4096^2 at 32000 velocities: 3549 -> 3254 ms) but the two extra branches
+// cost the 15-image search 80.4 -> 81.3 ms.
+#ifndef KBMI_SKIP_TAIL
+#define KBMI_SKIP_TAIL 1
+#endif
 #ifndef KBMI_INTERIOR
 #define KBMI_INTERIOR 1         // start rows with every displaced row in frame skip the row check
 #endif
@@ -520,7 +528,10 @@ __device__ __forceinline__ void visit_velocities(
 #pragma unroll
         for (int b = 0; b < NV; ++b) {
             if (b < from) continue;
-            if ((FMT == KB_F32 && b >= nl) || (b == NV - 1 && skip_last)) {
+            const bool tail = KBMI_SKIP_TAIL == 1
+                                  ? (b == NV - 1 && skip_last)
+                                  : (skip_last && b >= NV - KBMI_SKIP_TAIL && b >= n_img);
+            if ((FMT == KB_F32 && b >= nl) || tail) {
                 v[b] = LoadT{};
                 continue;
             }
@@ -647,7 +658,8 @@ __device__ __forceinline__ void visit_velocities(
         }
     };
     constexpr bool kPipe = PF && PIPE;
-    const bool skip_last = FMT == KB_F32 && !MB && n_img == NB - 1;
+    const bool skip_last = FMT == KB_F32 && !MB &&
+                           (KBMI_SKIP_TAIL == 1 ? n_img == NB - 1 : n_img >= NB - KBMI_SKIP_TAIL);
     // 16-bit planes of more than one batch keep every image's scales in LDS
     // (read per batch), up to kMaxLdsScaleImages images.
     constexpr int kMaxLdsScaleImages = kSearchScaleWords / 2;
