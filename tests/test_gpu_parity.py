@@ -268,8 +268,8 @@ def _errors(nu, al, vel, ref):
 @pytest.mark.parametrize("lp", ["f16", "bf16"])
 def test_survey_precision_mode_sampled(torch_dev, lp):
     """Precision mode on the survey stack (15 x 4096^2, 600 velocities, K = 50):
-    16-bit planes searched with K' = 50 and 64 candidates, then re-scored in
-    FP32.  On the sampled start pixels: nu/alpha error against the FP64
+    16-bit planes searched with the mode's K' (50 for FP16, 52 for BF16) and
+    with 64 candidates, then re-scored in FP32.  On the sampled start pixels: nu/alpha error against the FP64
     oracle before and after the re-score, and recall of the top-K (an entry
     counts when the oracle ranks it in its top K or within the nu tolerance
     of its K-th value).  Recall is statistical (parity unpinned), measured."""
@@ -286,7 +286,8 @@ def test_survey_precision_mode_sampled(torch_dev, lp):
     ws = lib.alloc_workspace(n, h, w, s.vel.shape[0], dev)
     yt, xt = torch.from_numpy(ys).to(dev), torch.from_numpy(xs).to(dev)
     kth = ref["nu"][:, s.k - 1].astype(np.float64)
-    for kc in (50, 64):
+    # bench.py's K': K for FP16, K + 2 for BF16
+    for kc in (s.k if lp == "f16" else s.k + 2, 64):
         cand = lib.search(src, s.t, s.vel, kc, workspace=ws, lp_scale=sc)
         res = lib.topk(cand, s.k, n, rescore=(planes, s.t, s.vel, ws))
         torch.cuda.synchronize()
@@ -307,7 +308,7 @@ def test_survey_precision_mode_sampled(torch_dev, lp):
              f"{a_nu.max():.2e}, alpha err max {a_al.max():.2e}; recall {recall:.5f}")
         assert a_nu.max() <= 1e-5 and a_al.max() <= 1e-5
         assert np.array_equal(r[3], ref["all_nobs"][r[2], np.arange(ys.size)[:, None]])
-        assert recall >= 0.99
+        assert recall >= 0.999
 
 
 @pytest.mark.parametrize("kc,k", [(50, 50), (50, 17), (64, 64), (7, 3), (1, 1)])
