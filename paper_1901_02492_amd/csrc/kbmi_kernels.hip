@@ -49,7 +49,13 @@ struct PsfTaps {
 constexpr int PP_TW = 64;       // output tile width
 constexpr int PP_TH = 16;       // output tile height
 constexpr int PP_THREADS = 256; // 4 waves; each thread produces 4 columns of one row
-constexpr int PP_LH = PP_TH + KB_MAX_PSF - 1;
+// LDS of one tile with its halo for a PSF of ph rows and PW columns: the
+// (a, w) pairs, then the validity bytes (sized at launch, so a small PSF
+// leaves room for more resident workgroups).
+template <int PW>
+constexpr size_t psi_phi_lds_bytes(int ph) {
+    return (size_t)(PP_TH + ph - 1) * (size_t)(PP_TW + PW - 1) * (sizeof(float2) + 1);
+}
 
 // psi = a (x) T and phi = w (x) T^2 (cross-correlations with zero padding) for
 // one 64 x 16 output tile of one image, with a = valid * img / var and
@@ -67,8 +73,9 @@ __global__ __launch_bounds__(PP_THREADS) void psi_phi_kernel(
     constexpr int LW = PP_TW + PW - 1;        // staged columns (even: PW is odd)
     constexpr int SEG = 4 + PW - 1;           // pixels one thread reads per PSF row
     static_assert(PW % 2 == 1 && LW % 2 == 0 && SEG % 2 == 0, "odd PSF widths only");
-    __shared__ float2 s_aw[PP_LH * LW];
-    __shared__ uint8_t s_ok[PP_LH * LW];
+    extern __shared__ __align__(16) unsigned char pp_lds[];
+    float2 *s_aw = reinterpret_cast<float2 *>(pp_lds);
+    uint8_t *s_ok = pp_lds + (size_t)(PP_TH + ph - 1) * LW * sizeof(float2);
 
     const int i = blockIdx.z;
     const int tx0 = blockIdx.x * PP_TW;
@@ -800,8 +807,9 @@ kb_status kb_make_psi_phi(const float *img, const float *var, const uint8_t *mas
     switch (psf_w) {
 #define KB_PSF_W(PW)                                                                         \
     case PW:                                                                                 \
-        hipLaunchKernelGGL(psi_phi_kernel<PW>, grid, dim3(PP_THREADS), 0, s, img, var, mask, \
-                           (int)h, (int)w, (int)psf_h, taps, pp, maxabs);                   \
+        hipLaunchKernelGGL(psi_phi_kernel<PW>, grid, dim3(PP_THREADS),                       \
+                           psi_phi_lds_bytes<PW>((int)psf_h), s, img, var, mask, (int)h,      \
+                           (int)w, (int)psf_h, taps, pp, maxabs);                           \
         break;
         KB_PSF_W(1) KB_PSF_W(3) KB_PSF_W(5) KB_PSF_W(7) KB_PSF_W(9) KB_PSF_W(11) KB_PSF_W(13)
         KB_PSF_W(15) KB_PSF_W(17) KB_PSF_W(19) KB_PSF_W(21) KB_PSF_W(23) KB_PSF_W(25)
