@@ -75,6 +75,42 @@ __device__ __forceinline__ uint64_t gather_light_curve(int64_t p, int j, int h, 
     return obs;
 }
 
+// J / d and H / d, each correctly rounded (IEEE double), by the hardware's
+// division sequence: scale the divisor and the numerator against each other,
+// refine the reciprocal of the scaled divisor (two Newton steps), form the
+// quotient, correct it with a fused residual and fix up the special cases.
+// The refined reciprocal depends only on the scaled divisor, so H's quotient
+// reuses J's wherever both numerators leave the divisor scaled alike (always,
+// short of exponents 2^1000 apart); elsewhere H's is refined on its own.  Each
+// quotient takes exactly the steps of a division of its own.
+__device__ __forceinline__ double refined_rcp(double ds) {
+    const double r = __builtin_amdgcn_rcp(ds);
+    const double e0 = __builtin_fma(-ds, r, 1.0);
+    const double r1 = __builtin_fma(r, e0, r);
+    const double e1 = __builtin_fma(-ds, r1, 1.0);
+    return __builtin_fma(r1, e1, r1);
+}
+__device__ __forceinline__ double quotient(double a, double d, double ds, double r) {
+    bool flag;
+    const double ns = __builtin_amdgcn_div_scale(a, d, true, &flag);
+    const double m = ns * r;
+    const double rem = __builtin_fma(-ds, m, ns);
+    return __builtin_amdgcn_div_fixup(__builtin_amdgcn_div_fmas(rem, r, m, flag), d, a);
+}
+__device__ __forceinline__ void divide_pair(double &J, double &H, double d) {
+    bool unused;
+    const double dsj = __builtin_amdgcn_div_scale(J, d, false, &unused);
+    const double dsh = __builtin_amdgcn_div_scale(H, d, false, &unused);
+    const double rj = refined_rcp(dsj);
+    double rh = rj;
+    const bool alike = __double_as_longlong(dsj) == __double_as_longlong(dsh);
+    if (__builtin_expect(__any(!alike), 0)) {
+        if (!alike) rh = refined_rcp(dsh);
+    }
+    J = quotient(J, d, dsj, rj);
+    H = quotient(H, d, dsh, rh);
+}
+
 // One round of the filter over the kept observations: the largest squared
 // standardised residual (-1 if none is kept) and, in `worst`, its image (the
 // lowest among equal values).
@@ -94,8 +130,7 @@ __device__ __forceinline__ double filter_round(const float2 (&v)[NB], uint64_t k
             if (seen && walk) {
                 const double s = q * (ti - tp);
                 const double d = 1.0 + s * J;
-                J = J / d;
-                H = H / d;
+                divide_pair(J, H, d);
             }
             Jf[i] = J;
             Hf[i] = H;
@@ -118,8 +153,7 @@ __device__ __forceinline__ double filter_round(const float2 (&v)[NB], uint64_t k
             if (seen && walk) {
                 const double s = q * (tp - ti);
                 const double d = 1.0 + s * J;
-                J = J / d;
-                H = H / d;
+                divide_pair(J, H, d);
             }
             const double ps = (double)v[i].x, ph = (double)v[i].y;
             const double Jk = Jf[i] + J, Hk = Hf[i] + H;
